@@ -1,0 +1,195 @@
+/*
+ * wdirac.h -- C ABI of libwdirac, the MI355X (gfx950) Wilson-Dirac library.
+ *
+ * The library applies the Wilson-Dirac operator
+ *
+ *     M psi(x) = psi(x) - kappa * D_hop psi(x),
+ *     D_hop psi(x) = sum_mu [ (1 - gamma_mu) U_mu(x) psi(x + mu)
+ *                           + (1 + gamma_mu) U_mu(x - mu)^dagger psi(x - mu) ],
+ *
+ * with SU(3) links U and 4-spin x 3-colour fields on a 4-D lattice, its hopping
+ * term restricted to even or odd sites ("Dslash", the paper's Section 4 "Wilson
+ * inverter: main features"), the even-odd preconditioned operator
+ * 1 - kappa^2 D_eo D_oe (caption of the paper's Fig. 2, Section 7), and a
+ * conjugate-gradient solver with double-precision global sums (Section 4).
+ * Gamma matrices are in the DeGrand-Rossi basis; mu = 0..3 is x, y, z, t.
+ * Boundary conditions are a sign bc[mu] = +1 / -1 applied on the hop across
+ * the lattice edge in direction mu.
+ *
+ * Conventions shared by every entry point
+ * --------------------------------------
+ * - Every function is extern "C", returns a wd_status (or a plain value where
+ *   stated) and never throws or aborts.  On WD_EINVAL / WD_ESHAPE /
+ *   WD_EUNSUPPORTED nothing is written.  wd_last_error() gives a thread-local
+ *   description of the last failure.
+ * - Field and weight buffers are DEVICE pointers owned by the caller (e.g. a
+ *   torch tensor's data_ptr()), sized with wd_spinor_bytes / wd_feature_bytes.
+ *   The library never frees them and keeps them past a call only where a
+ *   function says so (wd_batch).  Only wd_gauge_upload accepts a host pointer.
+ * - Work is enqueued on the context's HIP stream and is asynchronous, except
+ *   where a function returns host scalars (reductions, solvers, autotune),
+ *   which synchronise that stream.  An asynchronous device error is reported
+ *   as WD_EHIP by the next synchronising call.
+ * - Lattice dims X, Y, Z, T must be even and >= 2; the half volume V/2 must be
+ *   below 2^31.  Sites are split by parity (x+y+z+t)&1; inside a parity a site
+ *   has checkerboard index cb = lex >> 1, lex = x + X(y + Y(z + Z t)).
+ *
+ * Canonical (host-order) layouts, interleaved re, im doubles:
+ *   links            [4][T][Z][Y][X][3][3][2]      U_mu(x)[row][col]
+ *   spinor FULL      [nrhs][T][Z][Y][X][4][3][2]   [spin][colour]
+ *   spinor EVEN/ODD  [nrhs][V/2][4][3][2]          sites of that parity in cb order
+ * Packed (device) layouts are internal; wd_spinor_bytes gives their size.  A
+ * packed FULL field is the EVEN half followed by the ODD half, per rhs.
+ */
+#ifndef WDIRAC_H
+#define WDIRAC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define WD_ABI_VERSION 1
+
+typedef enum {
+    WD_OK = 0,
+    WD_EINVAL = 1,        /* bad argument: null pointer, bad enum, bad size   */
+    WD_ESHAPE = 2,        /* lattice dims or field shapes do not fit          */
+    WD_ENOMEM = 3,        /* device allocation failed                          */
+    WD_EHIP = 4,          /* a HIP runtime call or kernel failed               */
+    WD_ENOCONV = 5,       /* solver reached maxiter; x holds the last iterate  */
+    WD_ENAN = 6,          /* NaN or Inf met in a solver reduction              */
+    WD_EUNSUPPORTED = 7   /* valid but unsupported combination                 */
+} wd_status;
+
+/* Storage precision of links and fields.  F16 / BF16 store 16-bit values with
+ * a per-site float32 scale for spinors and compute in float32; F32 stores and
+ * computes in float32; F64 in float64. */
+typedef enum { WD_F64 = 0, WD_F32 = 1, WD_F16 = 2, WD_BF16 = 3 } wd_prec;
+
+/* Link storage: 18 reals, or 12 reals (rows 0 and 1) with row 2 rebuilt on
+ * the fly as conj(row0 x row1) (paper, Sections 4, 5 and 7). */
+typedef enum { WD_RECON_12 = 12, WD_RECON_18 = 18 } wd_recon;
+
+typedef enum { WD_FULL = 0, WD_EVEN = 1, WD_ODD = 2 } wd_subset;
+
+typedef struct {
+    int dims[4];   /* X, Y, Z, T: each even, >= 2                        */
+    int bc[4];     /* +1 periodic, -1 antiperiodic, per direction         */
+} wd_lattice;
+
+typedef struct wd_context_s* wd_context;   /* device, stream, workspace, tuning table */
+typedef struct wd_gauge_s* wd_gauge;       /* device link storage of one field        */
+typedef struct wd_batch_s* wd_batch;       /* a captured batch of dslash applications  */
+
+/* ---- version and errors ------------------------------------------------- */
+int wd_abi_version(void);
+const char* wd_status_string(int status);
+/* Thread-local text for the most recent failing call on this thread. */
+const char* wd_last_error(void);
+
+/* ---- context -------------------------------------------------------------- */
+/* Bind a context to HIP device `device` and stream `stream` (a hipStream_t, or
+ * NULL for the null stream).  Owns the solver workspace (allocated on first
+ * use, freed by wd_context_destroy) and the tuning table. */
+wd_status wd_context_create(int device, void* stream, wd_context* out);
+wd_status wd_context_set_stream(wd_context ctx, void* stream);
+wd_status wd_context_destroy(wd_context ctx);
+
+/* ---- gauge field (paper, Section 5: 18 floats per link, or 12 before
+ *      reconstruction) ------------------------------------------------------- */
+/* Create an empty gauge object for lattice `lat` with link storage `recon`.
+ * The lattice (dims and bc) is copied. */
+wd_status wd_gauge_create(wd_context ctx, const wd_lattice* lat, wd_recon recon, wd_gauge* out);
+/* Upload canonical float64 links (layout above; host pointer if on_device == 0,
+ * device pointer otherwise).  Synchronous.  Packed copies per precision are
+ * built from this field on first use of that precision (wd_gauge_prepare
+ * builds them ahead of time). */
+wd_status wd_gauge_upload(wd_gauge g, const double* links, int on_device);
+wd_status wd_gauge_prepare(wd_gauge g, wd_prec prec);
+/* Bytes of packed device link storage at precision `prec` (0 on bad input). */
+size_t wd_gauge_bytes(wd_gauge g, wd_prec prec);
+wd_status wd_gauge_destroy(wd_gauge g);
+
+/* ---- spinor fields (paper, Section 5: 24 floats per site, split by parity,
+ *      stored as structure-of-arrays of 16-byte vectors) ---------------------- */
+/* Bytes of a packed field; 0 on bad input. */
+size_t wd_spinor_bytes(const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs);
+/* canonical float64 (device) -> packed (device), and back.  16-bit precisions
+ * quantise each site with scale s = max |v_i| over its 24 float32 values and
+ * codes RNE16(v_i * RN(1/s)). */
+wd_status wd_spinor_pack(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                         const double* canon, void* packed);
+wd_status wd_spinor_unpack(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                           const void* packed, double* canon);
+/* dst = src converted between packed precisions (same subset, nrhs). */
+wd_status wd_spinor_convert(wd_context ctx, const wd_lattice* lat, wd_subset subset, int nrhs,
+                            wd_prec src_prec, const void* src, wd_prec dst_prec, void* dst);
+
+/* ---- operators (paper, Sections 4 and 7) --------------------------------- */
+/* out = D_hop in restricted to the sites of out_subset:
+ *   WD_EVEN: out_e = D_eo in_o (in is an ODD field), WD_ODD: out_o = D_oe in_e,
+ *   WD_FULL: out = D_hop in (both FULL fields).
+ * dagger != 0 applies D_hop^dagger.  Links and fields share precision `prec`. */
+wd_status wd_dslash(wd_gauge g, wd_subset out_subset, int dagger, wd_prec prec, int nrhs,
+                    const void* in, void* out);
+/* out = a * x + b * D_hop in  (x has the subset and precision of out; x may alias out). */
+wd_status wd_dslash_xpay(wd_gauge g, wd_subset out_subset, int dagger, wd_prec prec, int nrhs,
+                         const void* in, const void* x, double a, double b, void* out);
+/* subset WD_FULL: out = M in = in - kappa D_hop in (M^dagger if dagger);
+ * WD_EVEN: out = (1 - kappa^2 D_eo D_oe) in on even sites; WD_ODD: 1 - kappa^2 D_oe D_eo.
+ * in and out must not alias. */
+wd_status wd_apply_M(wd_gauge g, double kappa, wd_subset subset, int dagger, wd_prec prec, int nrhs,
+                     const void* in, void* out);
+/* out = M^dagger M in (FULL) or Mhat^dagger Mhat in (EVEN / ODD).  in and out must not alias. */
+wd_status wd_apply_MdagM(wd_gauge g, double kappa, wd_subset subset, wd_prec prec, int nrhs,
+                         const void* in, void* out);
+
+/* ---- global sums in float64 (paper, Section 4) ---------------------------- */
+/* result[0] + i result[1] = <a, b> = sum conj(a_i) b_i over the whole field
+ * (all rhs).  Deterministic: fixed-order two-pass reduction.  Synchronous. */
+wd_status wd_dot(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                 const void* a, const void* b, double* result);
+wd_status wd_norm2(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                   const void* a, double* result);
+/* y = alpha * x + y with complex alpha = (alpha_re, alpha_im); F32 and F64 only. */
+wd_status wd_caxpy(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                   double alpha_re, double alpha_im, const void* x, void* y);
+
+/* ---- solvers (paper, Section 4: even-odd preconditioned CG) --------------- */
+typedef struct {
+    double tol;        /* stop when ||r|| / ||b|| <= tol (true residual, float64) */
+    int maxiter;       /* iteration cap; WD_ENOCONV when reached                   */
+    int sloppy;        /* wd_prec of the inner iterations (F64, F32, F16, BF16)    */
+    double delta;      /* reliable update when ||r|| < delta * max ||r|| since last */
+    int pure_sloppy;   /* 1: never recompute the residual (reports the stall level) */
+} wd_solver_params;
+
+typedef struct {
+    int iters;              /* CG iterations                                      */
+    int reliable_updates;   /* float64 residual recomputations                    */
+    int operator_applies;   /* applications of the solved operator                */
+    int status;             /* wd_status of the solve                             */
+    double true_resid;      /* ||b - A x|| / ||b|| in float64, A the solved operator */
+    double true_resid_M;    /* ||b - M x|| / ||b|| for wd_wilson_solve, else -1     */
+    double seconds;         /* wall time from call to return                      */
+} wd_solver_info;
+
+/* Solve A x = b, A = M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD), by CG.
+ * b and x are float64 packed fields; x holds the initial guess on entry.  The
+ * iterations run in params->sloppy with float64 reliable updates.  Synchronous. */
+wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solver_params* params,
+                      const void* b, void* x, wd_solver_info* info);
+/* Solve M x = b on the full lattice through the even-odd Schur complement:
+ * b'_e = b_e + kappa D_eo b_o, CG on Mhat^dagger Mhat x_e = Mhat^dagger b'_e,
+ * x_o = b_o + kappa D_oe x_e.  b, x: FULL float64 packed fields.  Reports
+ * ||b - M x|| / ||b|| in true_resid_M.  Synchronous. */
+wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
+                          const void* b, void* x, wd_solver_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WDIRAC_H */

@@ -139,6 +139,17 @@ def site_parity(dims):
     return (x + y + z + t) & 1
 
 
+_PARITY_INDEX = {}
+
+
+def parity_sites(dims, parity):
+    """Lexicographic indices of the sites of one parity, in checkerboard order."""
+    key = (tuple(dims), parity)
+    if key not in _PARITY_INDEX:
+        _PARITY_INDEX[key] = np.flatnonzero(site_parity(dims).ravel() == parity)
+    return _PARITY_INDEX[key]
+
+
 def eo_split(field, dims, parity, site_ndim=2):
     """Sites of one parity in checkerboard order.
 
@@ -147,25 +158,23 @@ def eo_split(field, dims, parity, site_ndim=2):
     order is increasing cb = lex >> 1.
     """
     X, Y, Z, T = dims
-    par = site_parity(dims).ravel()
     nbatch = field.ndim - 4 - site_ndim
     lead, site = field.shape[:nbatch], field.shape[nbatch + 4:]
     if field.shape[nbatch:nbatch + 4] != (T, Z, Y, X):
         raise ValueError("field shape %r has no lattice axes %r" % (field.shape, (T, Z, Y, X)))
     flat = field.reshape(lead + (X * Y * Z * T,) + site)
-    return flat[(slice(None),) * nbatch + (par == parity,)]
+    return np.take(flat, parity_sites(dims, parity), axis=nbatch)
 
 
 def eo_merge(even, odd, dims, site_ndim=2):
     """Inverse of eo_split: two (*batch, Vh, *site) halves -> (*batch, T, Z, Y, X, *site)."""
     X, Y, Z, T = dims
-    par = site_parity(dims).ravel()
     nbatch = even.ndim - 1 - site_ndim
     lead, site = even.shape[:nbatch], even.shape[nbatch + 1:]
-    out = np.zeros(lead + (X * Y * Z * T,) + site, dtype=np.result_type(even, odd))
+    out = np.empty(lead + (X * Y * Z * T,) + site, dtype=np.result_type(even, odd))
     idx = (slice(None),) * nbatch
-    out[idx + (par == 0,)] = even
-    out[idx + (par == 1,)] = odd
+    out[idx + (parity_sites(dims, 0),)] = even
+    out[idx + (parity_sites(dims, 1),)] = odd
     return out.reshape(lead + (T, Z, Y, X) + site)
 
 
@@ -277,15 +286,16 @@ def quantize_spinor_sites(psi, kind):
     """16-bit storage of spinor sites with a per-site scale, decoded back.
 
     psi: complex (..., 4, 3) sites.  Per site: v = float32 of the 24 reals,
-    s = max |v_i| (float32), q_i = RNE16(v_i / s) (float32 division),
-    decoded value q_i * s (float32 product); s = 0 decodes to zeros.
+    s = max |v_i| (float32), inv = RN(1 / s) (float32), q_i = RNE16(RN(v_i * inv)),
+    decoded value RN(q_i * s) (float32 product); s = 0 decodes to zeros.
     Returns (decoded complex128, s float32, q float32-valued codes).
     """
     re = np.stack([psi.real, psi.imag], axis=-1).astype(np.float32)  # (..., 4, 3, 2)
     v = re.reshape(re.shape[:-3] + (24,))
     s = np.max(np.abs(v), axis=-1).astype(np.float32)
     safe = np.where(s > 0, s, np.float32(1.0)).astype(np.float32)
-    q = round16((v / safe[..., None]).astype(np.float32), kind)
+    inv = (np.float32(1.0) / safe).astype(np.float32)
+    q = round16((v * inv[..., None]).astype(np.float32), kind)
     dec = (q * safe[..., None]).astype(np.float32)
     dec = np.where(s[..., None] > 0, dec, np.float32(0.0))
     dec = dec.reshape(re.shape).astype(np.float64)

@@ -1,0 +1,390 @@
+// Vector updates and float64 global sums on packed fields (paper Section 4:
+// the dot product is a global sum done by the GPU in double precision by
+// parallel reduction; the other solver steps are BLAS-like kernels).
+//
+// A field is a run of `nhalves` half fields, each holding Vh sites of 24
+// reals; element-wise kernels walk sites, so every packed precision and
+// subset shares one code path.  Reductions are deterministic: a fixed grid of
+// workgroups each reduces a fixed strided set of sites (wave shuffles, then
+// LDS), and one workgroup sums the partials in a fixed order.
+#include <type_traits>
+
+#include "wd_core.h"
+
+namespace wd {
+
+constexpr int RED_BLOCK = 256;
+constexpr int RED_MAXBLOCKS = 2048;
+
+struct SiteRange {
+    const char* base;
+    int Vh;
+    size_t hb;   // bytes of one half field
+    __device__ __forceinline__ const char* half(long long h) const { return base + (size_t)h * hb; }
+};
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Reduce N values over the workgroup; thread 0 writes partials[n * nblk + blockIdx.x].
+template <int N> __device__ __forceinline__ void block_reduce(double* v, double* partials)
+{
+    __shared__ double lds[N][RED_BLOCK / 64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        double s = wave_sum(v[n]);
+        if (lane == 0) lds[n][wave] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            double s = 0.0;
+            for (int w = 0; w < RED_BLOCK / 64; ++w) s += lds[n][w];
+            partials[(size_t)n * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+__global__ void __launch_bounds__(RED_BLOCK) finish_kernel(const double* __restrict__ partials, int nblk, int n,
+                                                           double* __restrict__ out)
+{
+    __shared__ double lds[RED_BLOCK / 64];
+    for (int k = 0; k < n; ++k) {
+        double s = 0.0;
+        for (int i = threadIdx.x; i < nblk; i += RED_BLOCK) s += partials[(size_t)k * nblk + i];
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < RED_BLOCK / 64; ++w) t += lds[w];
+            out[k] = t;
+        }
+        __syncthreads();
+    }
+}
+
+static int red_blocks(long long nsites)
+{
+    long long b = (nsites + RED_BLOCK - 1) / RED_BLOCK;
+    return (int)(b < RED_MAXBLOCKS ? (b < 1 ? 1 : b) : RED_MAXBLOCKS);
+}
+
+static wd_status finish(wd_context ctx, int nblk, int n, bool fetch)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, n, ctx->dres);
+    WD_LAUNCHED();
+    if (fetch) return fetch_results(ctx, n);
+    return WD_OK;
+}
+
+wd_status fetch_results(wd_context ctx, int n)
+{
+    WD_HIP(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    WD_HIP(hipStreamSynchronize(ctx->stream));
+    return WD_OK;
+}
+
+// ---- dot / norm ------------------------------------------------------------------
+template <int P, bool DOT>
+__global__ void __launch_bounds__(RED_BLOCK) dot_kernel(SiteRange A, SiteRange B, long long nsites, double* partials)
+{
+    double acc[2] = {0.0, 0.0};
+    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = k / A.Vh;
+        const uint32_t cb = (uint32_t)(k - h * A.Vh);
+        typename RealOf<P>::T a[24];
+        SpinorIO<P>::load(A.half(h), A.Vh, cb, a);
+        if constexpr (DOT) {
+            typename RealOf<P>::T b[24];
+            SpinorIO<P>::load(B.half(h), B.Vh, cb, b);
+#pragma unroll
+            for (int i = 0; i < 12; ++i) {
+                const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+                acc[0] += ar * br + ai * bi;   // Re conj(a) b
+                acc[1] += ar * bi - ai * br;   // Im conj(a) b
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 24; ++i) acc[0] += (double)a[i] * (double)a[i];
+        }
+    }
+    block_reduce<DOT ? 2 : 1>(acc, partials);
+}
+
+template <int P, bool DOT>
+static wd_status dot_t(wd_context ctx, const Geom& g, size_t nh, const void* a, const void* b, bool fetch)
+{
+    const long long n = (long long)nh * g.Vh;
+    const int nblk = red_blocks(n);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2));
+    SiteRange A{(const char*)a, g.Vh, half_bytes(g, P)}, B{(const char*)b, g.Vh, half_bytes(g, P)};
+    hipLaunchKernelGGL((dot_kernel<P, DOT>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials);
+    WD_LAUNCHED();
+    return finish(ctx, nblk, DOT ? 2 : 1, fetch);
+}
+
+wd_status blas_dot(wd_context ctx, const Geom& g, size_t nh, int prec, const void* a, const void* b, bool fetch)
+{
+    switch (prec) {
+    case WD_F64: return dot_t<P_F64, true>(ctx, g, nh, a, b, fetch);
+    case WD_F32: return dot_t<P_F32, true>(ctx, g, nh, a, b, fetch);
+    case WD_F16: return dot_t<P_F16, true>(ctx, g, nh, a, b, fetch);
+    case WD_BF16: return dot_t<P_BF16, true>(ctx, g, nh, a, b, fetch);
+    }
+    set_error("dot: bad precision %d", prec);
+    return WD_EINVAL;
+}
+
+wd_status blas_norm2(wd_context ctx, const Geom& g, size_t nh, int prec, const void* a, bool fetch)
+{
+    switch (prec) {
+    case WD_F64: return dot_t<P_F64, false>(ctx, g, nh, a, a, fetch);
+    case WD_F32: return dot_t<P_F32, false>(ctx, g, nh, a, a, fetch);
+    case WD_F16: return dot_t<P_F16, false>(ctx, g, nh, a, a, fetch);
+    case WD_BF16: return dot_t<P_BF16, false>(ctx, g, nh, a, a, fetch);
+    }
+    set_error("norm2: bad precision %d", prec);
+    return WD_EINVAL;
+}
+
+// ---- element-wise ----------------------------------------------------------------
+#define WD_SITE_LOOP(nsites, Vh)                                                                         \
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;                                 \
+    if (k >= (nsites)) return;                                                                            \
+    const long long h = k / (Vh);                                                                         \
+    const uint32_t cb = (uint32_t)(k - h * (Vh));
+
+static dim3 site_grid(long long n) { return dim3((unsigned)((n + 255) / 256)); }
+
+template <int P>
+__global__ void caxpy_kernel(SiteRange X, SiteRange Y, long long n, double ar, double ai)
+{
+    WD_SITE_LOOP(n, X.Vh)
+    using T = typename RealOf<P>::T;
+    T x[24], y[24];
+    SpinorIO<P>::load(X.half(h), X.Vh, cb, x);
+    SpinorIO<P>::load(Y.half(h), Y.Vh, cb, y);
+    const T a = (T)ar, b = (T)ai;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        const T xr = x[2 * i], xi = x[2 * i + 1];
+        y[2 * i] += a * xr - b * xi;
+        y[2 * i + 1] += a * xi + b * xr;
+    }
+    SpinorIO<P>::store((char*)Y.half(h), Y.Vh, cb, y);
+}
+
+wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nh, int prec, double ar, double ai, const void* x, void* y)
+{
+    const long long n = (long long)nh * g.Vh;
+    SiteRange X{(const char*)x, g.Vh, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, half_bytes(g, prec)};
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL(caxpy_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai); break;
+    case WD_F32: hipLaunchKernelGGL(caxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai); break;
+    default: set_error("caxpy: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+template <int P>
+__global__ void zero_kernel(char* base, int Vh, size_t hb, long long n)
+{
+    WD_SITE_LOOP(n, Vh)
+    typename RealOf<P>::T z[24];
+#pragma unroll
+    for (int i = 0; i < 24; ++i) z[i] = 0;
+    SpinorIO<P>::store(base + (size_t)h * hb, Vh, cb, z);
+}
+
+wd_status blas_zero(wd_context ctx, const Geom& g, size_t nh, int prec, void* x)
+{
+    const long long n = (long long)nh * g.Vh;
+    const size_t hb = half_bytes(g, prec);
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL(zero_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
+    case WD_F32: hipLaunchKernelGGL(zero_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
+    case WD_F16: hipLaunchKernelGGL(zero_kernel<P_F16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
+    case WD_BF16: hipLaunchKernelGGL(zero_kernel<P_BF16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
+    default: set_error("zero: bad precision %d", prec); return WD_EINVAL;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+// y = a x + b y, x at PX, y at PY; arithmetic in float64 if either is F64
+template <int PX, int PY>
+__global__ void axpby_kernel(SiteRange X, SiteRange Y, long long n, double a, double b)
+{
+    WD_SITE_LOOP(n, X.Vh)
+    using T = typename std::conditional<(PX == P_F64 || PY == P_F64), double, float>::type;
+    typename RealOf<PX>::T x[24];
+    typename RealOf<PY>::T y[24];
+    SpinorIO<PX>::load(X.half(h), X.Vh, cb, x);
+    SpinorIO<PY>::load(Y.half(h), Y.Vh, cb, y);
+#pragma unroll
+    for (int i = 0; i < 24; ++i) y[i] = (typename RealOf<PY>::T)((T)a * (T)x[i] + (T)b * (T)y[i]);
+    SpinorIO<PY>::store((char*)Y.half(h), Y.Vh, cb, y);
+}
+
+template <int PX>
+static wd_status axpby_x(wd_context ctx, long long n, SiteRange X, SiteRange Y, int py, double a, double b)
+{
+    switch (py) {
+    case WD_F64: hipLaunchKernelGGL((axpby_kernel<PX, P_F64>), site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, a, b); break;
+    case WD_F32: hipLaunchKernelGGL((axpby_kernel<PX, P_F32>), site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, a, b); break;
+    case WD_F16: hipLaunchKernelGGL((axpby_kernel<PX, P_F16>), site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, a, b); break;
+    case WD_BF16: hipLaunchKernelGGL((axpby_kernel<PX, P_BF16>), site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, a, b); break;
+    default: set_error("axpby: bad precision %d", py); return WD_EINVAL;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nh, int px, const void* x, double a, int py, void* y, double b)
+{
+    const long long n = (long long)nh * g.Vh;
+    SiteRange X{(const char*)x, g.Vh, half_bytes(g, px)}, Y{(const char*)y, g.Vh, half_bytes(g, py)};
+    switch (px) {
+    case WD_F64: return axpby_x<P_F64>(ctx, n, X, Y, py, a, b);
+    case WD_F32: return axpby_x<P_F32>(ctx, n, X, Y, py, a, b);
+    case WD_F16: return axpby_x<P_F16>(ctx, n, X, Y, py, a, b);
+    case WD_BF16: return axpby_x<P_BF16>(ctx, n, X, Y, py, a, b);
+    }
+    set_error("axpby: bad precision %d", px);
+    return WD_EINVAL;
+}
+
+// ---- fused CG steps ------------------------------------------------------------------
+// x += alpha p ; r -= alpha Ap ; partial ||r||^2
+template <int PA, int PO>
+__global__ void __launch_bounds__(RED_BLOCK) cg_xr_kernel(SiteRange X, SiteRange R, SiteRange Pp, SiteRange AP,
+                                                          long long nsites, double alpha, double* partials)
+{
+    using T = typename RealOf<PA>::T;
+    double acc[1] = {0.0};
+    const T al = (T)alpha;
+    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = k / X.Vh;
+        const uint32_t cb = (uint32_t)(k - h * X.Vh);
+        T x[24], r[24];
+        typename RealOf<PO>::T p[24], ap[24];
+        SpinorIO<PO>::load(Pp.half(h), X.Vh, cb, p);
+        SpinorIO<PO>::load(AP.half(h), X.Vh, cb, ap);
+        SpinorIO<PA>::load(X.half(h), X.Vh, cb, x);
+        SpinorIO<PA>::load(R.half(h), X.Vh, cb, r);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            x[i] += al * (T)p[i];
+            r[i] -= al * (T)ap[i];
+            acc[0] += (double)r[i] * (double)r[i];
+        }
+        SpinorIO<PA>::store((char*)X.half(h), X.Vh, cb, x);
+        SpinorIO<PA>::store((char*)R.half(h), X.Vh, cb, r);
+    }
+    block_reduce<1>(acc, partials);
+}
+
+// p = r + beta p
+template <int PA, int PO>
+__global__ void cg_p_kernel(SiteRange R, SiteRange Pp, long long n, double beta)
+{
+    WD_SITE_LOOP(n, R.Vh)
+    using T = typename RealOf<PA>::T;
+    T r[24];
+    typename RealOf<PO>::T p[24];
+    SpinorIO<PA>::load(R.half(h), R.Vh, cb, r);
+    SpinorIO<PO>::load(Pp.half(h), R.Vh, cb, p);
+    const T be = (T)beta;
+#pragma unroll
+    for (int i = 0; i < 24; ++i) p[i] = (typename RealOf<PO>::T)(r[i] + be * (T)p[i]);
+    SpinorIO<PO>::store((char*)Pp.half(h), R.Vh, cb, p);
+}
+
+template <int PA, int PO>
+static wd_status cg_t(wd_context ctx, const Geom& g, size_t nh, void* x, void* r, const void* p, const void* ap, double alpha,
+                      bool fetch)
+{
+    const long long n = (long long)nh * g.Vh;
+    const int nblk = red_blocks(n);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk));
+    const size_t ha = half_bytes(g, PA), ho = half_bytes(g, PO);
+    SiteRange X{(const char*)x, g.Vh, ha}, R{(const char*)r, g.Vh, ha}, Pp{(const char*)p, g.Vh, ho}, AP{(const char*)ap, g.Vh, ho};
+    hipLaunchKernelGGL((cg_xr_kernel<PA, PO>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, X, R, Pp, AP, n, alpha,
+                       ctx->partials);
+    WD_LAUNCHED();
+    return finish(ctx, nblk, 1, fetch);
+}
+
+wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nh, int pacc, void* x, void* r, int pop, const void* p,
+                     const void* ap, double alpha, bool fetch)
+{
+    if (pacc == WD_F64 && pop == WD_F64) return cg_t<P_F64, P_F64>(ctx, g, nh, x, r, p, ap, alpha, fetch);
+    if (pacc == WD_F32 && pop == WD_F32) return cg_t<P_F32, P_F32>(ctx, g, nh, x, r, p, ap, alpha, fetch);
+    if (pacc == WD_F32 && pop == WD_F16) return cg_t<P_F32, P_F16>(ctx, g, nh, x, r, p, ap, alpha, fetch);
+    if (pacc == WD_F32 && pop == WD_BF16) return cg_t<P_F32, P_BF16>(ctx, g, nh, x, r, p, ap, alpha, fetch);
+    set_error("cg_xr: unsupported precision pair (%d, %d)", pacc, pop);
+    return WD_EUNSUPPORTED;
+}
+
+wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nh, int pacc, const void* r, int pop, void* p, double beta)
+{
+    const long long n = (long long)nh * g.Vh;
+    SiteRange R{(const char*)r, g.Vh, half_bytes(g, pacc)}, Pp{(const char*)p, g.Vh, half_bytes(g, pop)};
+    if (pacc == WD_F64 && pop == WD_F64)
+        hipLaunchKernelGGL((cg_p_kernel<P_F64, P_F64>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
+    else if (pacc == WD_F32 && pop == WD_F32)
+        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_F32>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
+    else if (pacc == WD_F32 && pop == WD_F16)
+        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_F16>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
+    else if (pacc == WD_F32 && pop == WD_BF16)
+        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_BF16>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
+    else {
+        set_error("cg_p: unsupported precision pair (%d, %d)", pacc, pop);
+        return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+// r = b - y, ||r||^2 (float64 fields)
+__global__ void __launch_bounds__(RED_BLOCK) xmy_norm_kernel(SiteRange B, SiteRange Y, SiteRange R, long long nsites,
+                                                             double* partials)
+{
+    double acc[1] = {0.0};
+    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = k / B.Vh;
+        const uint32_t cb = (uint32_t)(k - h * B.Vh);
+        double b[24], y[24];
+        SpinorIO<P_F64>::load(B.half(h), B.Vh, cb, b);
+        SpinorIO<P_F64>::load(Y.half(h), B.Vh, cb, y);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) {
+            b[i] -= y[i];
+            acc[0] += b[i] * b[i];
+        }
+        SpinorIO<P_F64>::store((char*)R.half(h), B.Vh, cb, b);
+    }
+    block_reduce<1>(acc, partials);
+}
+
+wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b, const void* y, void* r, bool fetch)
+{
+    const long long n = (long long)nh * g.Vh;
+    const int nblk = red_blocks(n);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk));
+    const size_t hb = half_bytes(g, WD_F64);
+    SiteRange B{(const char*)b, g.Vh, hb}, Y{(const char*)y, g.Vh, hb}, R{(const char*)r, g.Vh, hb};
+    hipLaunchKernelGGL(xmy_norm_kernel, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, Y, R, n, ctx->partials);
+    WD_LAUNCHED();
+    return finish(ctx, nblk, 1, fetch);
+}
+
+} // namespace wd

@@ -1,0 +1,243 @@
+// Conjugate gradient on the normal equations (paper Section 4: even-odd
+// preconditioned CG, every step a separate kernel, global sums in double
+// precision, the fields never leaving the device) with mixed precision:
+// the iterations run in a "sloppy" storage precision and the solution is
+// accumulated in float64 through reliable updates, each of which recomputes
+// the true residual b - A x in float64 (Sleijpen and van der Vorst's
+// reliable-update scheme).
+#include <chrono>
+#include <cmath>
+
+#include "wd_ops.h"
+
+namespace wd {
+
+struct CGProblem {
+    wd_gauge g;
+    double kappa;
+    int subset;
+    const void* c;       // right-hand side of A x = c (float64)
+    const void* bhat;    // non-null: also track ||bhat - Mhat x|| (Wilson-system residual)
+    double wnorm2;       // reference norm^2 for the Wilson-system residual
+};
+
+// r = c - A x in float64; ww = ||bhat - Mhat x||^2 when tracked.
+static wd_status true_residual(const CGProblem& P, const void* x, void* r, double* rr, double* ww)
+{
+    wd_context ctx = P.g->ctx;
+    const Geom& G = P.g->geom;
+    const size_t nh = halves_of(P.subset, 1);
+    const size_t bytes = half_bytes(G, WD_F64) * nh;
+    void *t1, *t2;
+    WD_TRY(ws_get(ctx, "cg.t1", bytes, &t1));
+    WD_TRY(ws_get(ctx, "cg.t2", bytes, &t2));
+    if (P.bhat) {
+        WD_TRY(op_M(P.g, P.kappa, P.subset, 0, WD_F64, 1, x, t1));
+        WD_TRY(blas_xmy_norm(ctx, G, nh, P.bhat, t1, t2, true));
+        *ww = ctx->hres[0];
+        WD_TRY(op_M(P.g, P.kappa, P.subset, 1, WD_F64, 1, t1, t2));
+    } else {
+        WD_TRY(op_MdagM(P.g, P.kappa, P.subset, WD_F64, 1, x, t2));
+        *ww = -1.0;
+    }
+    WD_TRY(blas_xmy_norm(ctx, G, nh, P.c, t2, r, true));
+    *rr = ctx->hres[0];
+    return WD_OK;
+}
+
+static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x, wd_solver_info* info)
+{
+    wd_context ctx = P.g->ctx;
+    const Geom& G = P.g->geom;
+    const int pop = prm.sloppy;
+    const int pacc = pop == WD_F64 ? WD_F64 : WD_F32;
+    const size_t nh = halves_of(P.subset, 1);
+    const bool pure = prm.pure_sloppy != 0;
+    const bool use_delta = pop != WD_F64 && prm.delta > 0.0;
+
+    void *r, *rs, *xs, *p, *ap;
+    WD_TRY(ws_get(ctx, "cg.r", half_bytes(G, WD_F64) * nh, &r));
+    WD_TRY(ws_get(ctx, "cg.rs", half_bytes(G, pacc) * nh, &rs));
+    WD_TRY(ws_get(ctx, "cg.xs", half_bytes(G, pacc) * nh, &xs));
+    WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &p));
+    WD_TRY(ws_get(ctx, "cg.ap", half_bytes(G, pop) * nh, &ap));
+
+    WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
+    const double cc = ctx->hres[0];
+    const double tol2 = prm.tol * prm.tol;
+    const double target_r = tol2 * cc;
+    const double target_w = tol2 * P.wnorm2;
+    info->iters = 0;
+    info->reliable_updates = 0;
+    info->operator_applies = 0;
+    if (!(cc > 0.0)) {
+        WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
+        info->true_resid = 0.0;
+        info->true_resid_M = P.bhat ? 0.0 : -1.0;
+        info->status = std::isfinite(cc) ? WD_OK : WD_ENAN;
+        return (wd_status)info->status;
+    }
+
+    double rr, ww;
+    WD_TRY(true_residual(P, x, r, &rr, &ww));
+    info->operator_applies++;
+    auto converged = [&]() { return P.bhat ? ww <= target_w : rr <= target_r; };
+    wd_status status = WD_ENOCONV;
+    if (converged()) status = WD_OK;
+
+    // sloppy residual level that triggers a float64 check of convergence
+    double trigger = P.bhat ? (ww > 0 ? rr / ww : 1.0) * target_w : target_r;
+    bool xs_dirty = false;
+    if (status != WD_OK) {
+        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pacc, rs));
+        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pop, p));
+        WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
+        double rr_s = rr, maxrr = rr;
+        while (info->iters < prm.maxiter) {
+            WD_TRY(op_MdagM(P.g, P.kappa, P.subset, pop, 1, p, ap));
+            info->operator_applies++;
+            WD_TRY(blas_dot(ctx, G, nh, pop, p, ap, true));
+            const double pap = ctx->hres[0];
+            if (!std::isfinite(pap) || !(pap > 0.0)) {
+                set_error("CG breakdown: <p, A p> = %g at iteration %d", pap, info->iters);
+                status = WD_ENAN;
+                break;
+            }
+            const double alpha = rr_s / pap;
+            WD_TRY(blas_cg_xr(ctx, G, nh, pacc, xs, rs, pop, p, ap, alpha, true));
+            xs_dirty = true;
+            double rr_new = ctx->hres[0];
+            info->iters++;
+            if (!std::isfinite(rr_new)) {
+                set_error("CG: non-finite residual at iteration %d", info->iters);
+                status = WD_ENAN;
+                break;
+            }
+            if (pure) {
+                if (rr_new <= trigger) break;
+            } else if ((use_delta && rr_new < prm.delta * prm.delta * maxrr) || rr_new <= trigger) {
+                // reliable update: fold the sloppy solution into x and recompute r in float64
+                WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+                WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
+                xs_dirty = false;
+                WD_TRY(true_residual(P, x, r, &rr, &ww));
+                info->operator_applies++;
+                info->reliable_updates++;
+                if (converged()) {
+                    status = WD_OK;
+                    break;
+                }
+                if (P.bhat && ww > 0) trigger = rr / ww * target_w;
+                WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pacc, rs));
+                rr_new = rr;
+                maxrr = rr;
+            }
+            if (rr_new > maxrr) maxrr = rr_new;
+            const double beta = rr_new / rr_s;
+            WD_TRY(blas_cg_p(ctx, G, nh, pacc, rs, pop, p, beta));
+            rr_s = rr_new;
+        }
+    }
+    if (xs_dirty) WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+    WD_TRY(true_residual(P, x, r, &rr, &ww));
+    info->operator_applies++;
+    info->true_resid = std::sqrt(rr / cc);
+    info->true_resid_M = P.bhat ? std::sqrt(ww / P.wnorm2) : -1.0;
+    if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
+    if (status == WD_ENOCONV)
+        set_error("CG did not reach tol %g in %d iterations (residual %g)", prm.tol, info->iters,
+                  P.bhat ? info->true_resid_M : info->true_resid);
+    info->status = status;
+    return status;
+}
+
+static wd_status check_params(const wd_solver_params* prm)
+{
+    if (!prm) {
+        set_error("solver params are NULL");
+        return WD_EINVAL;
+    }
+    if (!(prm->tol > 0.0) || prm->maxiter < 0 || !valid_prec(prm->sloppy) || prm->delta < 0.0 || prm->delta >= 1.0) {
+        set_error("bad solver params: tol %g, maxiter %d, sloppy %d, delta %g", prm->tol, prm->maxiter, prm->sloppy,
+                  prm->delta);
+        return WD_EINVAL;
+    }
+    return WD_OK;
+}
+
+} // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solver_params* params, const void* b,
+                      void* x, wd_solver_info* info)
+{
+    if (!g || !b || !x || !info) {
+        set_error("wd_cg_solve: NULL argument");
+        return WD_EINVAL;
+    }
+    WD_TRY(check_params(params));
+    if (!valid_subset(subset)) {
+        set_error("wd_cg_solve: bad subset %d", (int)subset);
+        return WD_EINVAL;
+    }
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    WD_HIP(hipStreamSynchronize(g->ctx->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    CGProblem P{g, kappa, (int)subset, b, nullptr, 0.0};
+    wd_status s = cg_run(P, *params, x, info);
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
+                          wd_solver_info* info)
+{
+    if (!g || !b || !x || !info) {
+        set_error("wd_wilson_solve: NULL argument");
+        return WD_EINVAL;
+    }
+    WD_TRY(check_params(params));
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    WD_HIP(hipStreamSynchronize(ctx->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    const long long hb = (long long)half_bytes(G, WD_F64);
+    const char* b_e = (const char*)b;
+    const char* b_o = b_e + hb;
+    char* x_e = (char*)x;
+    char* x_o = x_e + hb;
+    void *bhat, *c;
+    WD_TRY(ws_get(ctx, "wilson.bhat", hb, &bhat));
+    WD_TRY(ws_get(ctx, "wilson.c", hb, &c));
+    // bhat = b_e + kappa D_eo b_o ; c = Mhat^dagger bhat
+    WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, hb, bhat, hb, b_e, hb, 1.0, kappa));
+    WD_TRY(op_M(g, kappa, WD_EVEN, 1, WD_F64, 1, bhat, c));
+    WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
+    const double bb = ctx->hres[0];
+    CGProblem P{g, kappa, WD_EVEN, c, bhat, bb};
+    wd_status s = cg_run(P, *params, x_e, info);
+    if (s != WD_OK && s != WD_ENOCONV) return s;
+    // x_o = b_o + kappa D_oe x_e ; then the full-system residual in float64
+    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
+    void *t, *r;
+    WD_TRY(ws_get(ctx, "wilson.t", 2 * hb, &t));
+    WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
+    WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
+    WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
+    info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
+    info->operator_applies++;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+} // extern "C"

@@ -1,0 +1,135 @@
+// Host-side core of libwdirac: context, gauge objects, error reporting and
+// the launch entry points of each kernel family.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <string>
+
+#include "wd_device.h"
+#include "wdirac.h"
+
+namespace wd {
+
+// thread-local error text behind wd_last_error()
+void set_error(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
+void clear_error();
+
+#define WD_HIP(call)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            ::wd::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, __LINE__); \
+            return e_ == hipErrorOutOfMemory ? WD_ENOMEM : WD_EHIP;                                \
+        }                                                                                          \
+    } while (0)
+
+#define WD_TRY(expr)                      \
+    do {                                  \
+        wd_status s_ = (expr);            \
+        if (s_ != WD_OK) return s_;       \
+    } while (0)
+
+#define WD_LAUNCHED()                                                                   \
+    do {                                                                                \
+        hipError_t e_ = hipGetLastError();                                              \
+        if (e_ != hipSuccess) {                                                         \
+            ::wd::set_error("kernel launch failed: %s (%s:%d)", hipGetErrorString(e_), __FILE__, __LINE__); \
+            return WD_EHIP;                                                             \
+        }                                                                               \
+    } while (0)
+
+// Launch shape of one kernel: workgroup size, XCD-aware block remap, and
+// non-temporal (streaming) link loads.
+struct TuneParam {
+    int block = 256;
+    int remap = 1;
+    int nt = 0;
+};
+
+inline bool valid_prec(int p) { return p >= WD_F64 && p <= WD_BF16; }
+inline bool valid_subset(int s) { return s >= WD_FULL && s <= WD_ODD; }
+inline bool valid_recon(int r) { return r == WD_RECON_12 || r == WD_RECON_18; }
+
+// Bytes of one half field (Vh sites of one parity, one rhs) at precision p.
+inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (size_t)g.Vh; }
+inline size_t halves_of(int subset, int nrhs) { return (size_t)nrhs * (subset == WD_FULL ? 2 : 1); }
+
+wd_status make_geom(const wd_lattice* lat, Geom* g);
+
+} // namespace wd
+
+struct wd_context_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // named grow-only workspace buffers
+    std::map<std::string, std::pair<void*, size_t>> ws;
+    // reduction scratch: per-block partial sums and final scalars
+    double* partials = nullptr;
+    size_t npartials = 0;
+    double* dres = nullptr;    // device results
+    double* hres = nullptr;    // pinned host copy
+    std::map<std::string, wd::TuneParam> tune;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+struct wd_gauge_s {
+    wd_context ctx = nullptr;
+    wd_lattice lat{};
+    int recon = 12;
+    wd::Geom geom{};
+    double* canon = nullptr;       // float64 canonical links on the device
+    void* packed[4] = {nullptr, nullptr, nullptr, nullptr};   // per wd_prec
+    bool uploaded = false;
+};
+
+namespace wd {
+
+wd_status ws_get(wd_context ctx, const std::string& name, size_t bytes, void** out);
+wd_status ensure_reduction(wd_context ctx, size_t nblocks);
+wd_status gauge_links(wd_gauge g, int prec, const void** out);
+TuneParam tune_lookup(wd_context ctx, const std::string& key);
+
+// ---- dslash.hip -------------------------------------------------------------
+struct DslashCall {
+    const void* gauge = nullptr;   // packed links at `prec`
+    const void* in = nullptr;      // input half field, rhs 0 (parity 1 - par)
+    void* out = nullptr;           // output half field, rhs 0 (parity par)
+    const void* x = nullptr;       // xpay half field (parity par), or null
+    long long in_stride = 0, out_stride = 0, x_stride = 0;   // bytes between rhs
+    double a = 0.0, b = 1.0;       // out = a x + b D in  (or b D in without x)
+    int par = 0;
+    int nrhs = 1;
+    int dagger = 0;
+    int prec = WD_F32;
+    int recon = 12;
+};
+wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
+wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
+
+// ---- pack.hip ----------------------------------------------------------------
+wd_status launch_pack_gauge(wd_context ctx, const Geom& g, int prec, int recon, const double* canon, void* out);
+wd_status launch_spinor_pack(wd_context ctx, const Geom& g, int subset, int prec, int nrhs, const double* canon,
+                             void* packed, bool unpack);
+wd_status launch_convert(wd_context ctx, const Geom& g, size_t nhalves, int sp, const void* src, int dp, void* dst);
+
+// ---- blas.hip ----------------------------------------------------------------
+// All operate on `nhalves` consecutive half fields.  Reductions leave their
+// float64 results in ctx->dres and (when `fetch`) copy them to ctx->hres.
+wd_status blas_dot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, const void* b, bool fetch);
+wd_status blas_norm2(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, bool fetch);
+wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, double ar, double ai, const void* x, void* y);
+wd_status blas_zero(wd_context ctx, const Geom& g, size_t nhalves, int prec, void* x);
+// y = a*x + b*y with real a, b (y, x may differ in precision: x at px, y at py)
+wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nhalves, int px, const void* x, double a, int py, void* y, double b);
+// CG step: x += alpha p; r -= alpha Ap; ||r||^2 -> dres[0]  (x, r at pacc; p, Ap at pop)
+wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nhalves, int pacc, void* x, void* r, int pop, const void* p,
+                     const void* ap, double alpha, bool fetch);
+// CG step: p = r + beta p (r at pacc, p at pop)
+wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, const void* r, int pop, void* p, double beta);
+// r = b - y (all float64) and ||r||^2 -> dres[0]
+wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
+wd_status fetch_results(wd_context ctx, int n);
+
+} // namespace wd

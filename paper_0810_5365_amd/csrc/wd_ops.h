@@ -1,0 +1,19 @@
+// Operator composition shared by the C ABI and the solvers.
+#pragma once
+
+#include "wd_core.h"
+
+namespace wd {
+
+// out (parity par, nrhs half fields) = a x + b D in  (x may be null: out = b D in)
+wd_status hop_half(wd_gauge g, int prec, int par, int dagger, int nrhs, const void* in, long long in_stride, void* out,
+                   long long out_stride, const void* x, long long x_stride, double a, double b);
+// D_hop on a FULL / EVEN / ODD field, optionally fused with a x + b D in
+wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, const void* in, void* out, const void* x,
+                    double a, double b);
+// M (FULL) or Mhat (EVEN / ODD), or their daggers
+wd_status op_M(wd_gauge g, double kappa, int subset, int dagger, int prec, int nrhs, const void* in, void* out);
+// M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD)
+wd_status op_MdagM(wd_gauge g, double kappa, int subset, int prec, int nrhs, const void* in, void* out);
+
+} // namespace wd

@@ -1,0 +1,250 @@
+"""ctypes binding for libwdirac (argument marshalling only).
+
+Every function here forwards to the C ABI declared in include/wdirac.h under
+the same name; all computation runs in the library's HIP kernels.  PyTorch is
+used only to own device memory (uint8 tensors sized with wd_spinor_bytes)
+and to supply the HIP stream.  If libwdirac.so is missing this module raises
+at import: there is no fallback path.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwdirac.so")
+
+WD_OK, WD_EINVAL, WD_ESHAPE, WD_ENOMEM, WD_EHIP, WD_ENOCONV, WD_ENAN, WD_EUNSUPPORTED = range(8)
+F64, F32, F16, BF16 = 0, 1, 2, 3
+FULL, EVEN, ODD = 0, 1, 2
+RECON_12, RECON_18 = 12, 18
+PREC_NAMES = {F64: "f64", F32: "f32", F16: "f16", BF16: "bf16"}
+PREC_BY_NAME = {v: k for k, v in PREC_NAMES.items()}
+SUBSET_BY_NAME = {"full": FULL, "even": EVEN, "odd": ODD}
+
+
+class WdLattice(ctypes.Structure):
+    _fields_ = [("dims", ctypes.c_int * 4), ("bc", ctypes.c_int * 4)]
+
+
+class WdSolverParams(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("maxiter", ctypes.c_int), ("sloppy", ctypes.c_int),
+                ("delta", ctypes.c_double), ("pure_sloppy", ctypes.c_int)]
+
+
+class WdSolverInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("operator_applies", ctypes.c_int),
+                ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("true_resid_M", ctypes.c_double),
+                ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class WdError(RuntimeError):
+    def __init__(self, fn, status, detail):
+        self.status = status
+        super().__init__("%s -> %s: %s" % (fn, _lib.wd_status_string(status).decode(), detail))
+
+
+_V, _I, _D, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+_P = ctypes.POINTER
+# name: (restype, argtypes); restype int means a wd_status that is checked
+_PROTOS = {
+    "wd_abi_version": (_I, []),
+    "wd_status_string": (ctypes.c_char_p, [_I]),
+    "wd_last_error": (ctypes.c_char_p, []),
+    "wd_context_create": ("status", [_I, _V, _P(_V)]),
+    "wd_context_set_stream": ("status", [_V, _V]),
+    "wd_context_destroy": ("status", [_V]),
+    "wd_gauge_create": ("status", [_V, _P(WdLattice), _I, _P(_V)]),
+    "wd_gauge_upload": ("status", [_V, _V, _I]),
+    "wd_gauge_prepare": ("status", [_V, _I]),
+    "wd_gauge_bytes": (_S, [_V, _I]),
+    "wd_gauge_destroy": ("status", [_V]),
+    "wd_spinor_bytes": (_S, [_P(WdLattice), _I, _I, _I]),
+    "wd_spinor_pack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),
+    "wd_spinor_unpack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),
+    "wd_spinor_convert": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _I, _V]),
+    "wd_dslash": ("status", [_V, _I, _I, _I, _I, _V, _V]),
+    "wd_dslash_xpay": ("status", [_V, _I, _I, _I, _I, _V, _V, _D, _D, _V]),
+    "wd_apply_M": ("status", [_V, _D, _I, _I, _I, _I, _V, _V]),
+    "wd_apply_MdagM": ("status", [_V, _D, _I, _I, _I, _V, _V]),
+    "wd_dot": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V, _P(_D)]),
+    "wd_norm2": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _P(_D)]),
+    "wd_caxpy": ("status", [_V, _P(WdLattice), _I, _I, _I, _D, _D, _V, _V]),
+    "wd_cg_solve": ("status", [_V, _D, _I, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
+    "wd_wilson_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
+}
+
+_lib = None
+
+
+def _raw():
+    """The loaded CDLL (raises if the library is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libwdirac.so is not built (%s); run `python -m paper_0810_5365_amd.build`" % LIB_PATH)
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            f = getattr(lib, name)
+            f.restype = _I if res == "status" else res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    return list(_PROTOS)
+
+
+def _checked(name):
+    f = getattr(_raw(), name)
+
+    def call(*args, ok=(WD_OK,)):
+        s = f(*args)
+        if s not in ok:
+            raise WdError(name, s, _lib.wd_last_error().decode())
+        return s
+    call.__name__ = name
+    return call
+
+
+_raw()
+for _name, (_res, _args) in _PROTOS.items():
+    globals()[_name] = _checked(_name) if _res == "status" else getattr(_lib, _name)
+
+
+# ---------------------------------------------------------------------------
+# small conveniences (still marshalling only)
+# ---------------------------------------------------------------------------
+
+def lattice(dims, bc=(1, 1, 1, -1)):
+    lat = WdLattice()
+    for d in range(4):
+        lat.dims[d] = int(dims[d])
+        lat.bc[d] = int(bc[d])
+    return lat
+
+
+def _ptr(t):
+    """Device (or host) address of a torch tensor or numpy array."""
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+class Context:
+    """A library context bound to a device and a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        wd_context_create(int(device), ctypes.c_void_p(stream), ctypes.byref(h))
+        self.handle = h
+        self.device = device
+
+    def set_stream(self, stream):
+        wd_context_set_stream(self.handle, ctypes.c_void_p(stream))
+
+    def close(self):
+        if self.handle is not None:
+            wd_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Gauge:
+    def __init__(self, ctx, dims, bc=(1, 1, 1, -1), recon=RECON_12):
+        self.ctx = ctx
+        self.dims = tuple(dims)
+        self.bc = tuple(bc)
+        self.lat = lattice(dims, bc)
+        self.recon = recon
+        h = ctypes.c_void_p()
+        wd_gauge_create(ctx.handle, ctypes.byref(self.lat), int(recon), ctypes.byref(h))
+        self.handle = h
+
+    def upload(self, links):
+        """links: numpy complex128 (4, T, Z, Y, X, 3, 3) on the host, or a float64 torch tensor on the device."""
+        if isinstance(links, np.ndarray):
+            arr = np.ascontiguousarray(links, dtype=np.complex128)
+            wd_gauge_upload(self.handle, ctypes.c_void_p(arr.ctypes.data), 0)
+        else:
+            wd_gauge_upload(self.handle, ctypes.c_void_p(links.data_ptr()), 1)
+
+    def prepare(self, prec):
+        wd_gauge_prepare(self.handle, int(prec))
+
+    def close(self):
+        if self.handle is not None:
+            wd_gauge_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def spinor_bytes(lat, subset, prec, nrhs=1):
+    return int(wd_spinor_bytes(ctypes.byref(lat), int(subset), int(prec), int(nrhs)))
+
+
+def new_field(lat, subset, prec, nrhs=1, device=0):
+    """An uninitialised packed device field (torch uint8 tensor)."""
+    import torch
+    n = spinor_bytes(lat, subset, prec, nrhs)
+    if n == 0:
+        raise ValueError("bad field description")
+    return torch.empty(n, dtype=torch.uint8, device="cuda:%d" % device)
+
+
+def _check_field(t, lat, subset, prec, nrhs):
+    need = spinor_bytes(lat, subset, prec, nrhs)
+    got = t.numel() * t.element_size()
+    if got < need:
+        raise ValueError("field buffer holds %d bytes, needs %d" % (got, need))
+
+
+def pack(ctx, lat, subset, prec, canon, nrhs=1):
+    """canonical complex (numpy, host) or float64 (torch, device) -> new packed device field."""
+    import torch
+    if isinstance(canon, np.ndarray):
+        canon = torch.from_numpy(np.ascontiguousarray(canon, dtype=np.complex128).view(np.float64)).to(
+            "cuda:%d" % ctx.device)
+    out = new_field(lat, subset, prec, nrhs, ctx.device)
+    wd_spinor_pack(ctx.handle, ctypes.byref(lat), int(subset), int(prec), int(nrhs), ctypes.c_void_p(canon.data_ptr()),
+                   ctypes.c_void_p(out.data_ptr()))
+    return out
+
+
+def unpack(ctx, lat, subset, prec, packed, shape, nrhs=1):
+    """packed device field -> numpy complex128 of the given canonical shape."""
+    import torch
+    _check_field(packed, lat, subset, prec, nrhs)
+    n = int(np.prod(shape)) * 2
+    canon = torch.empty(n, dtype=torch.float64, device="cuda:%d" % ctx.device)
+    wd_spinor_unpack(ctx.handle, ctypes.byref(lat), int(subset), int(prec), int(nrhs), ctypes.c_void_p(packed.data_ptr()),
+                     ctypes.c_void_p(canon.data_ptr()))
+    torch.cuda.current_stream(ctx.device).synchronize()
+    return canon.cpu().numpy().view(np.complex128).reshape(shape)
+
+
+def solver_params(tol=1e-10, maxiter=10000, sloppy=F32, delta=0.1, pure_sloppy=False):
+    p = WdSolverParams()
+    p.tol = tol
+    p.maxiter = maxiter
+    p.sloppy = int(sloppy)
+    p.delta = delta
+    p.pure_sloppy = int(bool(pure_sloppy))
+    return p
