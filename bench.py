@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--dims", type=int, nargs=4, default=list(DIMS))
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
+    ap.add_argument("--no-extras", action="store_true", help="skip the multi-rhs and ragged-batch measurements")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON tuning table: loaded if it exists (no tuning), else tuned and written there")
     return ap.parse_args()
 
 
@@ -60,6 +64,73 @@ def cpu_baseline(U, psi_e, dims):
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": "%d application(s) of the FP64 oracle's Mhat^dag Mhat on the full %dx%dx%dx%d lattice "
                       "(%d even sites), %.2f s each" % (reps, *dims, Vh, dt)}
+
+
+def extras(w, ctx, stream, torch, ls):
+    """Multi-rhs (16 rhs on 16^3 x 32) and the ragged batch (8^4, 12^4, 16^3 x 32,
+    24^3 x 32 in one persistent graph launch): time per call and GFLOP/s."""
+    import ctypes
+    out = {}
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    dims, nrhs = (16, 16, 16, 32), 16
+    Vh = 16 * 16 * 16 * 32 // 2
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(ls.gauge_field(dims, 0.5, ls.link_seed(4)))
+    lat = w.lattice(dims, BC)
+    psi = ls.gaussian_complex((nrhs, Vh, 4, 3), ls.source_seed(4), ls.STREAM_SPINOR)
+    for prec in (w.F32, w.BF16):
+        name = w.PREC_NAMES[prec]
+        fin = w.pack(ctx, lat, w.ODD, prec, psi, nrhs)
+        fout = w.new_field(lat, w.EVEN, prec, nrhs)
+        w.wd_autotune_dslash(g.handle, prec, nrhs, None)
+        us = timed(lambda: w.wd_dslash(g.handle, w.EVEN, 0, prec, nrhs, fin.data_ptr(), fout.data_ptr()), 50)
+        # separate launches per rhs, for comparison
+        hb = w.spinor_bytes(lat, w.EVEN, prec)
+        us1 = timed(lambda: [w.wd_dslash(g.handle, w.EVEN, 0, prec, 1, fin.data_ptr() + r * hb, fout.data_ptr() + r * hb)
+                             for r in range(nrhs)], 10)
+        out["multi_rhs_16c32_%s" % name] = {
+            "nrhs": nrhs, "us_per_call": round(us, 2), "gflops": round(nrhs * Vh * FLOPS_DSLASH / us / 1e3, 1),
+            "us_one_rhs_per_launch": round(us1, 2), "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, nrhs, 0, 0))}
+    g.close()
+
+    specs = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 32)]
+    for prec in (w.F32, w.BF16):
+        items = (w.WdBatchItem * len(specs))()
+        keep = []
+        sites = 0
+        for i, d in enumerate(specs):
+            gi = w.Gauge(ctx, d, BC, 12)
+            gi.upload(ls.gauge_field(d, 0.5, ls.link_seed(4, i + 1)))
+            li = w.lattice(d, BC)
+            vh = d[0] * d[1] * d[2] * d[3] // 2
+            fi = w.pack(ctx, li, w.ODD, prec, ls.gaussian_complex((vh, 4, 3), ls.source_seed(4, i + 1), ls.STREAM_SPINOR))
+            fo = w.new_field(li, w.EVEN, prec)
+            items[i].gauge, items[i].out_subset, items[i].dagger, items[i].nrhs = gi.handle.value, w.EVEN, 0, 1
+            items[i].in_, items[i].out = fi.data_ptr(), fo.data_ptr()
+            keep.append((gi, fi, fo))
+            sites += vh
+        b = ctypes.c_void_p()
+        w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
+        us = timed(lambda: w.wd_batch_run(b), 50)
+        w.wd_batch_destroy(b)
+        out["ragged_batch_%s" % w.PREC_NAMES[prec]] = {
+            "lattices": ["%dx%dx%dx%d" % d for d in specs], "even_sites": sites, "launches_per_call": 1,
+            "us_per_call": round(us, 2), "gflops": round(sites * FLOPS_DSLASH / us / 1e3, 1)}
+        for gi, _, _ in keep:
+            gi.close()
+    return out
 
 
 def main():
@@ -89,6 +160,15 @@ def main():
     fin = w.pack(ctx, lat, w.EVEN, w.F32, psi_e)
     fout = w.new_field(lat, w.EVEN, w.F32)
     torch.cuda.synchronize()
+    tuned = {}
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        w.wd_tune_load(ctx.handle, args.tune_cache.encode())
+    elif not args.no_tune:
+        print("bench: autotuning the dslash launch shape", file=sys.stderr, flush=True)
+        w.wd_autotune_dslash(g.handle, w.F32, 1, args.tune_cache.encode() if args.tune_cache else None)
+    for dag in (0, 1):
+        for xp in (0, 1):
+            tuned["d%d_x%d" % (dag, xp)] = w.tune_get(ctx, w.dslash_key(dims, w.F32, 12, 1, dag, xp))
 
     def step():
         w.wd_apply_MdagM(g.handle, KAPPA, w.EVEN, w.F32, 1, fin.data_ptr(), fout.data_ptr())
@@ -108,6 +188,42 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
+
+    # the plain even-odd dslash D_eo alone (no fused update), same timing method
+    fodd = w.new_field(lat, w.ODD, w.F32)
+    fodd.zero_()
+    for _ in range(5):
+        w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fodd.data_ptr(), fout.data_ptr())
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    n_eo = max(args.steps, 20)
+    e0.record(stream)
+    for _ in range(n_eo):
+        w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fodd.data_ptr(), fout.data_ptr())
+    e1.record(stream)
+    torch.cuda.synchronize()
+    eo_us = e0.elapsed_time(e1) * 1e3 / n_eo
+    eo = {"us_per_launch": round(eo_us, 3), "gflops": round(Vh * FLOPS_DSLASH / eo_us / 1e3, 1),
+          "gbs_algorithmic": round(Vh * BYTES_DSLASH / eo_us / 1e3, 1),
+          "frac_hbm": round(Vh * BYTES_DSLASH / eo_us / 1e3 / HBM_PEAK_GBS, 4),
+          "gbs_naive_no_reuse": round(Vh * (8 * (48 + 96) + 96) / eo_us / 1e3, 1)}
+
+    # achievable ceiling: streaming copy of 2 GiB (read + write bytes counted)
+    nbytes = 2 << 30
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    for _ in range(3):
+        w.wd_device_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), nbytes)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(10):
+        w.wd_device_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), nbytes)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * nbytes * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
 
     flops_step = Vh * 2 * (2 * FLOPS_DSLASH + FLOPS_XPAY)
     gflops = flops_step / (ms_per_step * 1e-3) / 1e9
@@ -146,7 +262,14 @@ def main():
                      "kernel": "dslash_kernel<F32, r12> (4 launches/step, 2 with xpay)",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_launch_s * 1e6, 3)},
         "wall_s_timed": round(wall, 4),
+        "dslash_eo": eo,
+        "copy_gbs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
+        "tuned_launch": tuned,
     }
+    if not args.no_extras:
+        print("bench: multi-rhs and ragged-batch measurements", file=sys.stderr, flush=True)
+        rec["extras"] = extras(w, ctx, stream, torch, ls)
     if not args.no_cpu:
         print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(U, psi_e, dims)

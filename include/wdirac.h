@@ -188,6 +188,50 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
 wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
                           const void* b, void* x, wd_solver_info* info);
 
+/* ---- batches: many lattices and right-hand sides in one launch --------------- */
+typedef struct {
+    wd_gauge gauge;    /* links and lattice of this item (all items: one context, one wd_recon) */
+    int out_subset;    /* WD_EVEN (out_e = D_eo in_o) or WD_ODD (out_o = D_oe in_e)             */
+    int dagger;        /* nonzero: D_hop^dagger                                                 */
+    int nrhs;          /* right-hand sides: nrhs packed half fields, back to back               */
+    const void* in;    /* packed input half fields (device)                                    */
+    void* out;         /* packed output half fields (device)                                   */
+} wd_batch_item;
+/* Capture the even-odd hopping term of every item (lattices of any volume,
+ * each with its own nrhs) as ONE persistent kernel launch in a hipGraph.
+ * All items use precision prec.  The batch RETAINS the gauge objects and the
+ * in/out pointers: they must stay valid until wd_batch_destroy.  Links are
+ * packed at prec during this call.  Synchronous. */
+wd_status wd_batch_create(wd_context ctx, int n, const wd_batch_item* items, wd_prec prec, wd_batch* out);
+/* Replay the graph on the context's stream (one kernel launch).  Asynchronous. */
+wd_status wd_batch_run(wd_batch b);
+/* Number of tiles (256 output sites of one rhs) and persistent workgroups. */
+wd_status wd_batch_info(wd_batch b, long long* ntiles, int* grid);
+wd_status wd_batch_destroy(wd_batch b);
+
+/* ---- bandwidth reference ----------------------------------------------------- */
+/* dst = src for `bytes` bytes (a multiple of 16) with a streaming 16-byte-per-
+ * lane copy kernel: the achievable-bandwidth ceiling the dslash is compared
+ * with, and the reference for hardware byte counters.  Asynchronous. */
+wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t bytes);
+
+/* ---- launch-shape tuning --------------------------------------------------- */
+/* Time every launch shape of the dslash kernels used with gauge g at precision
+ * prec and nrhs right-hand sides (workgroup size 64..256, XCD-aware block
+ * remap, non-temporal link loads, software-pipelined directions and, for
+ * nrhs > 1, right-hand sides interleaved with the site tiles), for both
+ * dagger settings with and without the fused a x + b D in, and keep the
+ * fastest in the context's tuning table.  If cache_path is not NULL the file
+ * is read first and the whole table written back after.  Synchronous; uses
+ * three scratch half fields of the context workspace. */
+wd_status wd_autotune_dslash(wd_gauge g, wd_prec prec, int nrhs, const char* cache_path);
+/* Write / read the tuning table as JSON (a missing file reads as empty). */
+wd_status wd_tune_save(wd_context ctx, const char* path);
+wd_status wd_tune_load(wd_context ctx, const char* path);
+/* Look up one tuning entry by key; fills out5 = {block, remap, nt, pf,
+ * rhs_inner} and returns 1, or returns 0 if the key is absent. */
+int wd_tune_get(wd_context ctx, const char* key, int* out5);
+
 #ifdef __cplusplus
 }
 #endif

@@ -107,6 +107,8 @@ TuneParam tune_lookup(wd_context ctx, const std::string& key)
     if (const char* e = getenv("WD_DSLASH_BLOCK")) tp.block = atoi(e);
     if (const char* e = getenv("WD_DSLASH_REMAP")) tp.remap = atoi(e);
     if (const char* e = getenv("WD_DSLASH_NT")) tp.nt = atoi(e);
+    if (const char* e = getenv("WD_DSLASH_PF")) tp.pf = atoi(e);
+    if (const char* e = getenv("WD_DSLASH_RHS_INNER")) tp.rhs_inner = atoi(e);
     return tp;
 }
 

@@ -387,4 +387,43 @@ wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b,
     return finish(ctx, nblk, 1, fetch);
 }
 
+// ---- STREAM-style copy: the achievable HBM ceiling and the reference for
+// the hardware byte counters ------------------------------------------------------
+// Four 16-byte loads per work-item are issued before the four stores.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) copy_kernel(const f32x4* __restrict__ src, f32x4* __restrict__ dst, long long n)
+{
+    const long long stride = (long long)gridDim.x * 1024;
+    for (long long base = (long long)blockIdx.x * 1024 + threadIdx.x; base < n; base += stride) {
+        f32x4 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (base + 256 * j < n) v[j] = __builtin_nontemporal_load(&src[base + 256 * j]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (base + 256 * j < n) __builtin_nontemporal_store(v[j], &dst[base + 256 * j]);
+    }
+}
+
+wd_status launch_copy(wd_context ctx, const void* src, void* dst, size_t bytes)
+{
+    const long long n = (long long)(bytes / 16);
+    long long blocks = (n + 1023) / 1024;
+    if (blocks > 256 * 16) blocks = 256 * 16;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(copy_kernel, dim3((unsigned)blocks), dim3(256), 0, ctx->stream, (const f32x4*)src, (f32x4*)dst, n);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
 } // namespace wd
+
+extern "C" wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t bytes)
+{
+    if (!ctx || !src || !dst || bytes % 16) {
+        wd::set_error("wd_device_copy: NULL pointer or size not a multiple of 16");
+        return WD_EINVAL;
+    }
+    return wd::launch_copy(ctx, src, dst, bytes);
+}

@@ -1,0 +1,194 @@
+// Autotuner for the dslash launch shape: workgroup size, XCD-aware block
+// remap, non-temporal link loads and software pipelining of the directions
+// are timed with HIP events on scratch fields of the gauge's lattice; the
+// fastest shape per kernel variant goes into the context's tuning table,
+// which can be written to and read from a JSON file.
+//
+// The paper tunes by hand for occupancy (192 active threads per
+// multiprocessor, Section 6) and for the read path (Section 5); here the
+// same questions are answered by measurement on the target device.
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "wd_core.h"
+
+namespace wd {
+
+static std::string dslash_key(const Geom& g, int prec, int recon, int nrhs, int dagger, int xpay)
+{
+    char key[160];
+    snprintf(key, sizeof key, "dslash:%dx%dx%dx%d:p%d:r%d:n%d:d%d:x%d", g.L[0], g.L[1], g.L[2], g.L[3], prec, recon,
+             nrhs, dagger, xpay);
+    return key;
+}
+
+static wd_status time_launch(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp, int reps,
+                             float* us)
+{
+    for (int i = 0; i < 2; ++i) WD_TRY(launch_dslash_tuned(ctx, g, c, tp));
+    WD_HIP(hipEventRecord(ctx->ev0, ctx->stream));
+    for (int i = 0; i < reps; ++i) WD_TRY(launch_dslash_tuned(ctx, g, c, tp));
+    WD_HIP(hipEventRecord(ctx->ev1, ctx->stream));
+    WD_HIP(hipEventSynchronize(ctx->ev1));
+    float ms = 0.f;
+    WD_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+    *us = ms * 1000.f / reps;
+    return WD_OK;
+}
+
+wd_status tune_save(wd_context ctx, const char* path)
+{
+    FILE* f = fopen(path, "w");
+    if (!f) {
+        set_error("cannot write tuning cache %s", path);
+        return WD_EINVAL;
+    }
+    fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
+    size_t i = 0;
+    for (auto& kv : ctx->tune) {
+        fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d, \"ri\": %d}%s\n",
+                kv.first.c_str(), kv.second.block, kv.second.remap, kv.second.nt, kv.second.pf, kv.second.rhs_inner,
+                ++i < ctx->tune.size() ? "," : "");
+    }
+    fprintf(f, "]}\n");
+    fclose(f);
+    return WD_OK;
+}
+
+wd_status tune_load(wd_context ctx, const char* path)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return WD_OK;   // no cache yet
+    char line[512];
+    while (fgets(line, sizeof line, f)) {
+        char key[256];
+        TuneParam tp;
+        const char* p = strstr(line, "{\"key\": \"");
+        if (!p) continue;
+        if (sscanf(p, "{\"key\": \"%255[^\"]\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d", key, &tp.block,
+                   &tp.remap, &tp.nt, &tp.pf) == 5) {
+            const char* ri = strstr(p, "\"ri\": ");
+            if (ri) tp.rhs_inner = atoi(ri + 6);
+            if (tp.block >= 64 && tp.block <= 256 && tp.block % 64 == 0) ctx->tune[key] = tp;
+        }
+    }
+    fclose(f);
+    return WD_OK;
+}
+
+wd_status autotune_dslash(wd_gauge g, int prec, int nrhs, int* ntuned)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    const void* links = nullptr;
+    WD_TRY(gauge_links(g, prec, &links));
+    const size_t hb = half_bytes(G, prec);
+    void *in, *out, *x;
+    WD_TRY(ws_get(ctx, "tune.in", hb * nrhs, &in));
+    WD_TRY(ws_get(ctx, "tune.out", hb * nrhs, &out));
+    WD_TRY(ws_get(ctx, "tune.x", hb * nrhs, &x));
+    WD_TRY(blas_zero(ctx, G, nrhs, prec, in));
+    WD_TRY(blas_zero(ctx, G, nrhs, prec, x));
+    // enough repetitions for ~1 ms of kernel time per candidate
+    const double est_us = 1e-3 * (double)G.Vh * nrhs * 0.15;
+    const int reps = est_us > 1000.0 ? 3 : (int)(1000.0 / (est_us + 1.0)) + 3;
+    *ntuned = 0;
+    for (int dagger = 0; dagger < 2; ++dagger)
+        for (int xpay = 0; xpay < 2; ++xpay) {
+            DslashCall c;
+            c.gauge = links;
+            c.in = in;
+            c.out = out;
+            c.x = xpay ? x : nullptr;
+            c.in_stride = c.out_stride = c.x_stride = (long long)hb;
+            c.a = 1.0;
+            c.b = -0.015;
+            c.par = 0;
+            c.nrhs = nrhs;
+            c.dagger = dagger;
+            c.prec = prec;
+            c.recon = g->recon;
+            TuneParam best;
+            float best_us = 1e30f;
+            for (int block = 64; block <= 256; block += 64)
+                for (int remap = 0; remap < 2; ++remap)
+                    for (int nt = 0; nt < 2; ++nt)
+                        for (int pf = 0; pf < 2; ++pf)
+                            for (int ri = (nrhs > 1 ? 0 : 1); ri < 2; ++ri) {
+                            TuneParam tp;
+                            tp.block = block;
+                            tp.remap = remap;
+                            tp.nt = nt;
+                            tp.pf = pf;
+                            tp.rhs_inner = ri;
+                            float us;
+                            WD_TRY(time_launch(ctx, G, c, tp, reps, &us));
+                            if (us < best_us) {
+                                best_us = us;
+                                best = tp;
+                            }
+                        }
+            ctx->tune[dslash_key(G, prec, g->recon, nrhs, dagger, xpay)] = best;
+            ++*ntuned;
+        }
+    return WD_OK;
+}
+
+} // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+wd_status wd_autotune_dslash(wd_gauge g, wd_prec prec, int nrhs, const char* cache_path)
+{
+    if (!g || !valid_prec(prec) || nrhs < 1 || nrhs > 65535) {
+        set_error("wd_autotune_dslash: bad argument");
+        return WD_EINVAL;
+    }
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    if (cache_path) WD_TRY(tune_load(g->ctx, cache_path));
+    int n = 0;
+    WD_TRY(autotune_dslash(g, prec, nrhs, &n));
+    if (cache_path) WD_TRY(tune_save(g->ctx, cache_path));
+    return WD_OK;
+}
+
+wd_status wd_tune_save(wd_context ctx, const char* path)
+{
+    if (!ctx || !path) {
+        set_error("wd_tune_save: NULL argument");
+        return WD_EINVAL;
+    }
+    return tune_save(ctx, path);
+}
+
+wd_status wd_tune_load(wd_context ctx, const char* path)
+{
+    if (!ctx || !path) {
+        set_error("wd_tune_load: NULL argument");
+        return WD_EINVAL;
+    }
+    return tune_load(ctx, path);
+}
+
+int wd_tune_get(wd_context ctx, const char* key, int* out5)
+{
+    if (!ctx || !key || !out5) return 0;
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) return 0;
+    out5[0] = it->second.block;
+    out5[1] = it->second.remap;
+    out5[2] = it->second.nt;
+    out5[3] = it->second.pf;
+    out5[4] = it->second.rhs_inner;
+    return 1;
+}
+
+} // extern "C"

@@ -45,7 +45,9 @@ void clear_error();
 struct TuneParam {
     int block = 256;
     int remap = 1;
-    int nt = 0;
+    int nt = 0;   // non-temporal link loads
+    int pf = 0;   // software-pipelined directions
+    int rhs_inner = 1;   // several rhs: interleave them with the site tiles
 };
 
 inline bool valid_prec(int p) { return p >= WD_F64 && p <= WD_BF16; }

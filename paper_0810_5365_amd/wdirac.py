@@ -10,6 +10,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its bundled HIP runtime must be the one the process loads, so
+# that libwdirac.so (NEEDED libamdhip64.so.7) binds to it instead of pulling a
+# second runtime copy from /opt/rocm that would not see the device.
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libwdirac.so")
@@ -39,6 +43,11 @@ class WdSolverInfo(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class WdBatchItem(ctypes.Structure):
+    _fields_ = [("gauge", ctypes.c_void_p), ("out_subset", ctypes.c_int), ("dagger", ctypes.c_int),
+                ("nrhs", ctypes.c_int), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p)]
 
 
 class WdError(RuntimeError):
@@ -75,6 +84,15 @@ _PROTOS = {
     "wd_caxpy": ("status", [_V, _P(WdLattice), _I, _I, _I, _D, _D, _V, _V]),
     "wd_cg_solve": ("status", [_V, _D, _I, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
     "wd_wilson_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
+    "wd_batch_create": ("status", [_V, _I, _P(WdBatchItem), _I, _P(_V)]),
+    "wd_batch_run": ("status", [_V]),
+    "wd_batch_info": ("status", [_V, _P(ctypes.c_longlong), _P(_I)]),
+    "wd_batch_destroy": ("status", [_V]),
+    "wd_device_copy": ("status", [_V, _V, _V, _S]),
+    "wd_autotune_dslash": ("status", [_V, _I, _I, ctypes.c_char_p]),
+    "wd_tune_save": ("status", [_V, ctypes.c_char_p]),
+    "wd_tune_load": ("status", [_V, ctypes.c_char_p]),
+    "wd_tune_get": (_I, [_V, ctypes.c_char_p, _P(_I)]),
 }
 
 _lib = None
@@ -238,6 +256,18 @@ def unpack(ctx, lat, subset, prec, packed, shape, nrhs=1):
                      ctypes.c_void_p(canon.data_ptr()))
     torch.cuda.current_stream(ctx.device).synchronize()
     return canon.cpu().numpy().view(np.complex128).reshape(shape)
+
+
+def dslash_key(dims, prec, recon, nrhs, dagger, xpay):
+    """Tuning-table key of one dslash kernel variant."""
+    return "dslash:%dx%dx%dx%d:p%d:r%d:n%d:d%d:x%d" % (tuple(dims) + (prec, recon, nrhs, int(dagger), int(xpay)))
+
+
+def tune_get(ctx, key):
+    out = (ctypes.c_int * 5)()
+    if wd_tune_get(ctx.handle, key.encode(), out):
+        return {"block": out[0], "remap": out[1], "nt": out[2], "pf": out[3], "rhs_inner": out[4]}
+    return None
 
 
 def solver_params(tol=1e-10, maxiter=10000, sloppy=F32, delta=0.1, pure_sloppy=False):

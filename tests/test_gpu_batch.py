@@ -1,0 +1,184 @@
+"""GPU: many right-hand sides and a ragged batch of lattices in one persistent
+launch replayed from a hipGraph, each lattice and each rhs checked against the
+FP64 oracle separately."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import lattice_synth as ls
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+@pytest.fixture(scope="module")
+def w():
+    from paper_0810_5365_amd import wdirac
+    return wdirac
+
+
+def half_source(dims, seed, nrhs):
+    X, Y, Z, T = dims
+    return ls.gaussian_complex((nrhs, X * Y * Z * T // 2, 4, 3), seed, ls.STREAM_SPINOR)
+
+
+def ref_hop(U, psi, out_subset_even, dagger):
+    return orc.d_eo(U, psi, BC, dagger) if out_subset_even else orc.d_oe(U, psi, BC, dagger)
+
+
+@pytest.mark.parametrize("rhs_inner", [0, 1])
+def test_multi_rhs_orderings(w, monkeypatch, rhs_inner):
+    monkeypatch.setenv("WD_DSLASH_RHS_INNER", str(rhs_inner))
+    dims, nrhs = (6, 4, 10, 4), 5
+    ctx = w.Context(0)
+    U = ls.gauge_field(dims, 0.5, 23)
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(U)
+    lat = w.lattice(dims, BC)
+    psi = half_source(dims, 9, nrhs)
+    fin = w.pack(ctx, lat, w.EVEN, w.F32, psi, nrhs)
+    fout = w.new_field(lat, w.ODD, w.F32, nrhs)
+    w.wd_dslash(g.handle, w.ODD, 0, w.F32, nrhs, fin.data_ptr(), fout.data_ptr())
+    got = w.unpack(ctx, lat, w.ODD, w.F32, fout, psi.shape, nrhs)
+    ref = orc.d_oe(U, psi, BC)
+    for r in range(nrhs):
+        assert orc.rel_l2(got[r], ref[r]) < 1e-5
+    g.close()
+    ctx.close()
+
+
+def _run_batch(w, ctx, specs, prec, replays=3):
+    """specs: list of (dims, out_even, dagger, nrhs, seed)."""
+    import torch
+    items = (w.WdBatchItem * len(specs))()
+    keep = []
+    for i, (dims, out_even, dagger, nrhs, seed) in enumerate(specs):
+        U = ls.gauge_field(dims, 0.5, seed)
+        g = w.Gauge(ctx, dims, BC, 12)
+        g.upload(U)
+        lat = w.lattice(dims, BC)
+        psi = half_source(dims, seed + 1, nrhs)
+        in_sub, out_sub = (w.ODD, w.EVEN) if out_even else (w.EVEN, w.ODD)
+        fin = w.pack(ctx, lat, in_sub, prec, psi, nrhs)
+        fout = w.new_field(lat, out_sub, prec, nrhs)
+        fout.zero_()
+        items[i].gauge = g.handle.value
+        items[i].out_subset = out_sub
+        items[i].dagger = dagger
+        items[i].nrhs = nrhs
+        items[i].in_ = fin.data_ptr()
+        items[i].out = fout.data_ptr()
+        keep.append((U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs))
+    b = ctypes.c_void_p()
+    w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
+    nt, grid = ctypes.c_longlong(), ctypes.c_int()
+    w.wd_batch_info(b, ctypes.byref(nt), ctypes.byref(grid))
+    results = []
+    for rep in range(replays):
+        for k in keep:
+            k[5].zero_()                     # eager work between replays
+        torch.cuda.synchronize()
+        w.wd_batch_run(b)
+        torch.cuda.synchronize()
+        outs = [w.unpack(ctx, k[2], k[6], prec, k[5], k[3].shape, k[9]) for k in keep]
+        results.append(outs)
+    w.wd_batch_destroy(b)
+    return keep, results, nt.value, grid.value
+
+
+def test_ragged_batch_one_launch_f32(w):
+    ctx = w.Context(0)
+    specs = [((8, 8, 8, 8), True, 0, 3, 101), ((12, 12, 12, 12), False, 1, 1, 102),
+             ((6, 4, 10, 4), True, 1, 2, 103), ((2, 2, 2, 2), False, 0, 1, 104)]
+    keep, results, ntiles, grid = _run_batch(w, ctx, specs, w.F32)
+    expect_tiles = sum(((d[0] * d[1] * d[2] * d[3] // 2 + 255) // 256) * n for d, _, _, n, _ in specs)
+    assert ntiles == expect_tiles and 1 <= grid <= ntiles
+    for outs in results:
+        for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
+            ref = ref_hop(U, psi, out_even, bool(dagger))
+            for r in range(nrhs):
+                assert orc.rel_l2(got[r], ref[r]) < 1e-5
+    for k in keep:
+        k[1].close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f16"])
+def test_ragged_batch_16bit(w, prec):
+    ctx = w.Context(0)
+    specs = [((8, 8, 8, 8), True, 0, 2, 201), ((12, 12, 12, 12), True, 0, 1, 202), ((4, 6, 2, 10), False, 1, 3, 203)]
+    keep, results, _, _ = _run_batch(w, ctx, specs, w.PREC_BY_NAME[prec], replays=2)
+    for outs in results:
+        for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
+            ref = ref_hop(U, psi, out_even, bool(dagger))
+            for r in range(nrhs):
+                assert orc.rel_l2(got[r], ref[r]) < 5e-3
+    for k in keep:
+        k[1].close()
+    ctx.close()
+
+
+def test_batch_rejects_bad_items(w):
+    ctx = w.Context(0)
+    dims = (4, 4, 4, 4)
+    g12 = w.Gauge(ctx, dims, BC, 12)
+    g12.upload(ls.gauge_field(dims, 0.5, 1))
+    g18 = w.Gauge(ctx, dims, BC, 18)
+    g18.upload(ls.gauge_field(dims, 0.5, 1))
+    lat = w.lattice(dims, BC)
+    f = w.new_field(lat, w.EVEN, w.F32)
+    items = (w.WdBatchItem * 2)()
+    for i, g in enumerate((g12, g18)):
+        items[i].gauge = g.handle.value
+        items[i].out_subset = w.EVEN
+        items[i].dagger = 0
+        items[i].nrhs = 1
+        items[i].in_ = f.data_ptr()
+        items[i].out = f.data_ptr()
+    b = ctypes.c_void_p()
+    lib = w._raw()
+    assert lib.wd_batch_create(ctx.handle, 2, items, w.F32, ctypes.byref(b)) == w.WD_EUNSUPPORTED
+    items[1].gauge = g12.handle.value
+    items[1].out_subset = w.FULL
+    assert lib.wd_batch_create(ctx.handle, 2, items, w.F32, ctypes.byref(b)) == w.WD_EINVAL
+    assert lib.wd_batch_create(ctx.handle, 0, items, w.F32, ctypes.byref(b)) == w.WD_EINVAL
+    g12.close()
+    g18.close()
+    ctx.close()
+
+
+def test_sixteen_rhs_on_16c32(w):
+    """The multi-rhs workload at full size: 16 Gaussian right-hand sides on 16^3 x 32."""
+    dims, nrhs = (16, 16, 16, 32), 16
+    ctx = w.Context(0)
+    U = ls.gauge_field(dims, 0.5, ls.link_seed(4))
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(U)
+    lat = w.lattice(dims, BC)
+    psi = half_source(dims, ls.source_seed(4), nrhs)
+    ref = orc.d_eo(U, psi, BC)
+    for prec, tol in ((w.F32, 1e-5), (w.BF16, 5e-3)):
+        fin = w.pack(ctx, lat, w.ODD, prec, psi, nrhs)
+        fout = w.new_field(lat, w.EVEN, prec, nrhs)
+        w.wd_dslash(g.handle, w.EVEN, 0, prec, nrhs, fin.data_ptr(), fout.data_ptr())
+        got = w.unpack(ctx, lat, w.EVEN, prec, fout, psi.shape, nrhs)
+        for r in range(nrhs):
+            assert orc.rel_l2(got[r], ref[r]) < tol
+    g.close()
+    ctx.close()
+
+
+def test_ragged_batch_full_size_lattices(w):
+    """The ragged workload at its real sizes: 8^4, 12^4, 16^3 x 32 and 24^3 x 32 in one launch."""
+    ctx = w.Context(0)
+    specs = [((8, 8, 8, 8), True, 0, 1, 4101), ((12, 12, 12, 12), True, 0, 1, 4102),
+             ((16, 16, 16, 32), True, 0, 1, 4103), ((24, 24, 24, 32), True, 0, 1, 4104)]
+    keep, results, _, _ = _run_batch(w, ctx, specs, w.F32, replays=2)
+    for outs in results:
+        for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
+            assert orc.rel_l2(got[0], ref_hop(U, psi, out_even, False)[0]) < 1e-5
+    for k in keep:
+        k[1].close()
+    ctx.close()
