@@ -46,6 +46,28 @@ def parse():
     return ap.parse_args()
 
 
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_0810_5365_amd", "csrc")
+    for f in ("dslash_body.h", "dslash.hip", "wd_device.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the kernel sources as they are now (else None)."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "dslash_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_src_sha256") != kernel_source_sha() or DIMS != (32, 32, 32, 64):
+        return None
+    return rec.get("bytes_per_launch")
+
+
 def cpu_baseline(U, psi_e, dims):
     """The FP64 oracle's Mhat^dagger Mhat on the same inputs (one application)."""
     import oracle as orc
@@ -233,13 +255,7 @@ def main():
     bytes_per_launch = Vh * (BYTES_DSLASH + BYTES_XPAY / 2.0)   # averaged over the 4 launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
 
-    traffic = None
-    tr_path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "dslash_f32_r12_32c64_traffic.json")
-    if os.path.exists(tr_path):
-        try:
-            traffic = json.load(open(tr_path)).get("bytes_per_launch")
-        except Exception:
-            traffic = None
+    traffic = measured_traffic()
 
     rec = {
         "metric": "dslash GFLOP/s & %HBM roofline; time to 1e-10 solve, plain vs mixed+learned",

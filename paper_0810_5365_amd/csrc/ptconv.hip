@@ -1,0 +1,533 @@
+// Parallel-transport convolution: the gauge-equivariant layer of the learned
+// preconditioner.  A feature field holds C colour triplets per site; a layer
+// maps C_in channels to C_out channels with nine paths p (stay, +mu, -mu):
+//
+//     psi^a(x) = sum_p sum_b W[p, a, b] (T_p phi^b)(x),
+//     T_0 phi = phi,  T_{+mu} phi(x) = U_mu(x) s+ phi(x + mu),
+//     T_{-mu} phi(x) = U_mu(x - mu)^dagger s- phi(x - mu),
+//
+// with the same links, boundary signs and even-odd site storage as the
+// Wilson hopping term (one work-item per output site, links shared by all
+// channels of a direction).  Gradients (PyTorch's convention for complex
+// parameters, dL/dRe + i dL/dIm):
+//     input:  gin^b = sum_p T_p^dagger sum_a conj(W[p, a, b]) gout^a
+//             = the same layer with adjoint weights W'[p', b, a] = conj(W[p, a, b])
+//               (p' swaps +mu and -mu), so it reuses the forward kernel;
+//     weight: gW[p, a, b] = sum_x sum_c gout^a(x)_c conj((T_p phi^b)(x)_c), a lattice
+//             reduction done per path with float64 partial sums.
+//
+// Packed feature layout (float32): sample n, channel c, parity par, colour k,
+// site cb -> float2 at (((n C + c) 2 + par) 3 + k) Vh + cb.
+#include "wd_core.h"
+
+namespace wd {
+
+struct PTArgs {
+    const char* gauge;      // packed float32 links
+    const float2* in;       // features (C_in channels)
+    float2* out;            // features (C_out channels)
+    const void* W;          // [9][C_out][C_in] complex at wprec
+    Geom g;
+    int cin;
+    long long in_sample, out_sample;   // float2 elements between samples
+};
+
+__device__ __forceinline__ size_t fidx(int c, int par, int k, int Vh, uint32_t cb)
+{
+    return ((size_t)(c * 2 + par) * 3 + k) * Vh + cb;
+}
+
+template <int WP> __device__ __forceinline__ float2 load_w(const void* W, int i)
+{
+    if constexpr (WP == P_F32) {
+        return ((const float2*)W)[i];
+    } else {
+        const uint32_t q = ((const uint32_t*)W)[i];
+        return make_float2(h2f<WP>(q), h2f<WP>(q >> 16));
+    }
+}
+
+template <typename T> __device__ __forceinline__ void mat_vec(const T* u, const T* v, T* w, bool dag)
+{
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T re = 0, im = 0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const int e = dag ? (3 * b + a) : (3 * a + b);
+            const T ur = u[2 * e], ui = dag ? -u[2 * e + 1] : u[2 * e + 1];
+            re += ur * v[2 * b] - ui * v[2 * b + 1];
+            im += ur * v[2 * b + 1] + ui * v[2 * b];
+        }
+        w[2 * a] = re;
+        w[2 * a + 1] = im;
+    }
+}
+
+// Accumulate W[p] (T_p phi) over all input channels for one path.
+template <int COUT, int WP>
+__device__ __forceinline__ void mix_path(const PTArgs& A, int p, const float2* in, int par, uint32_t cb, const float* u,
+                                         bool dag, float sign, bool transport, float* acc)
+{
+    const int Vh = A.g.Vh;
+    for (int b = 0; b < A.cin; ++b) {
+        float v[6], t[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 q = in[fidx(b, par, k, Vh, cb)];
+            v[2 * k] = q.x;
+            v[2 * k + 1] = q.y;
+        }
+        if (transport) {
+            mat_vec(u, v, t, dag);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] *= sign;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] = v[i];
+        }
+#pragma unroll
+        for (int a = 0; a < COUT; ++a) {
+            const float2 w = load_w<WP>(A.W, (p * COUT + a) * A.cin + b);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                acc[6 * a + 2 * k] += w.x * t[2 * k] - w.y * t[2 * k + 1];
+                acc[6 * a + 2 * k + 1] += w.x * t[2 * k + 1] + w.y * t[2 * k];
+            }
+        }
+    }
+}
+
+template <int MU, bool FWD, int R, int COUT, int WP>
+__device__ __forceinline__ void ptconv_dir(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
+                                           float* acc)
+{
+    const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
+    const int lpar = FWD ? par : 1 - par;
+    const uint32_t lcb = FWD ? cb : nb;
+    float u[18];
+    LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.Vh, A.g.Vh, lcb, u);
+    const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
+    mix_path<COUT, WP>(A, FWD ? 1 + MU : 5 + MU, in, 1 - par, nb, u, !FWD, sign, true, acc);
+}
+
+template <int R, int COUT, int WP>
+__global__ void __launch_bounds__(256) ptconv_fwd_kernel(PTArgs A)
+{
+    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t Vh = (uint32_t)A.g.Vh;
+    if (idx >= 2 * Vh) return;
+    const int par = idx >= Vh ? 1 : 0;
+    const uint32_t cb = idx - (uint32_t)par * Vh;
+    const float2* in = A.in + (size_t)blockIdx.y * A.in_sample;
+    float2* out = A.out + (size_t)blockIdx.y * A.out_sample;
+    int c[4];
+    cb_coords(A.g, cb, par, c);
+    float acc[6 * COUT];
+#pragma unroll
+    for (int i = 0; i < 6 * COUT; ++i) acc[i] = 0.f;
+    mix_path<COUT, WP>(A, 0, in, par, cb, nullptr, false, 1.f, false, acc);
+    ptconv_dir<0, true, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<1, true, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<2, true, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<3, true, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<0, false, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<1, false, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<2, false, R, COUT, WP>(A, in, par, cb, c, acc);
+    ptconv_dir<3, false, R, COUT, WP>(A, in, par, cb, c, acc);
+#pragma unroll
+    for (int a = 0; a < COUT; ++a)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) out[fidx(a, par, k, A.g.Vh, cb)] = make_float2(acc[6 * a + 2 * k], acc[6 * a + 2 * k + 1]);
+}
+
+// W'[p'][b][a] = conj(W[p][a][b]) with p' = p for the stay path and +mu <-> -mu.
+template <int WP>
+__global__ void adjoint_weights_kernel(const void* W, void* Wt, int cin, int cout)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 9 * cin * cout) return;
+    const int p = i / (cin * cout);
+    const int r = i - p * cin * cout;
+    const int b = r / cout, a = r - b * cout;       // Wt index: [p'][b][a]
+    const int pp = p == 0 ? 0 : (p <= 4 ? p + 4 : p - 4);
+    const int src = (pp * cout + a) * cin + b;
+    if constexpr (WP == P_F32) {
+        const float2 w = ((const float2*)W)[src];
+        ((float2*)Wt)[i] = make_float2(w.x, -w.y);
+    } else {
+        const uint32_t q = ((const uint32_t*)W)[src];
+        ((uint32_t*)Wt)[i] = q ^ 0x80000000u;   // negate the imaginary half
+    }
+}
+
+// gW partials: grid (nblk, 9 paths); each workgroup reduces its sites for every (b, a).
+template <int R, int COUT>
+__global__ void __launch_bounds__(256) ptconv_wgrad_kernel(PTArgs A, const float2* __restrict__ gout, int nsamples,
+                                                           double* __restrict__ partials)
+{
+    const int p = blockIdx.y;
+    const uint32_t Vh = (uint32_t)A.g.Vh;
+    const long long nsites = 2ll * Vh * nsamples;
+    __shared__ double lds[2 * COUT][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int b = 0; b < A.cin; ++b) {
+        double acc[2 * COUT];
+#pragma unroll
+        for (int i = 0; i < 2 * COUT; ++i) acc[i] = 0.0;
+        for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < nsites; k += (long long)gridDim.x * 256) {
+            const int n = (int)(k / (2 * Vh));
+            const uint32_t idx = (uint32_t)(k - (long long)n * 2 * Vh);
+            const int par = idx >= Vh ? 1 : 0;
+            const uint32_t cb = idx - (uint32_t)par * Vh;
+            const float2* in = A.in + (size_t)n * A.in_sample;
+            const float2* go = gout + (size_t)n * A.out_sample;
+            float t[6];
+            if (p == 0) {
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    const float2 q = in[fidx(b, par, kk, Vh, cb)];
+                    t[2 * kk] = q.x;
+                    t[2 * kk + 1] = q.y;
+                }
+            } else {
+                int c[4];
+                cb_coords(A.g, cb, par, c);
+                const int mu = (p - 1) & 3;
+                const bool fwd = p <= 4;
+                uint32_t nb;
+                bool edge;
+                switch (mu * 2 + (fwd ? 0 : 1)) {
+                case 0: nb = neighbour<0, true>(A.g, cb, c); edge = on_boundary<0, true>(A.g, c); break;
+                case 1: nb = neighbour<0, false>(A.g, cb, c); edge = on_boundary<0, false>(A.g, c); break;
+                case 2: nb = neighbour<1, true>(A.g, cb, c); edge = on_boundary<1, true>(A.g, c); break;
+                case 3: nb = neighbour<1, false>(A.g, cb, c); edge = on_boundary<1, false>(A.g, c); break;
+                case 4: nb = neighbour<2, true>(A.g, cb, c); edge = on_boundary<2, true>(A.g, c); break;
+                case 5: nb = neighbour<2, false>(A.g, cb, c); edge = on_boundary<2, false>(A.g, c); break;
+                case 6: nb = neighbour<3, true>(A.g, cb, c); edge = on_boundary<3, true>(A.g, c); break;
+                default: nb = neighbour<3, false>(A.g, cb, c); edge = on_boundary<3, false>(A.g, c); break;
+                }
+                const int lpar = fwd ? par : 1 - par;
+                const uint32_t lcb = fwd ? cb : nb;
+                float u[18], v[6];
+                LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * mu + lpar) * link_site_bytes(P_F32, R) * Vh, Vh, lcb, u);
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    const float2 q = in[fidx(b, 1 - par, kk, Vh, nb)];
+                    v[2 * kk] = q.x;
+                    v[2 * kk + 1] = q.y;
+                }
+                mat_vec(u, v, t, !fwd);
+                const float s = edge ? A.g.bcf[mu] : 1.0f;
+#pragma unroll
+                for (int i = 0; i < 6; ++i) t[i] *= s;
+            }
+#pragma unroll
+            for (int a = 0; a < COUT; ++a) {
+                float re = 0.f, im = 0.f;
+#pragma unroll
+                for (int kk = 0; kk < 3; ++kk) {
+                    const float2 gq = go[fidx(a, par, kk, Vh, cb)];
+                    // g * conj(t)
+                    re += gq.x * t[2 * kk] + gq.y * t[2 * kk + 1];
+                    im += gq.y * t[2 * kk] - gq.x * t[2 * kk + 1];
+                }
+                acc[2 * a] += re;
+                acc[2 * a + 1] += im;
+            }
+        }
+        // workgroup reduction of the 2 COUT values
+#pragma unroll
+        for (int i = 0; i < 2 * COUT; ++i) {
+            double s = acc[i];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+            if (lane == 0) lds[i][wave] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * COUT) {
+            const double s = lds[threadIdx.x][0] + lds[threadIdx.x][1] + lds[threadIdx.x][2] + lds[threadIdx.x][3];
+            // partials[((p * cin + b) * 2 COUT + i) * nblk + block]
+            partials[((size_t)(p * A.cin + b) * 2 * COUT + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// gW[p][a][b] (float32 complex) from the partials, in a fixed order.
+__global__ void wgrad_finish_kernel(const double* __restrict__ partials, int nblk, int cin, int cout, float2* __restrict__ gW)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;   // over (p, b, a)
+    if (i >= 9 * cin * cout) return;
+    const int p = i / (cin * cout);
+    const int r = i - p * cin * cout;
+    const int b = r / cout, a = r - b * cout;
+    double re = 0.0, im = 0.0;
+    const double* pr = partials + ((size_t)(p * cin + b) * 2 * cout + 2 * a) * nblk;
+    const double* pi = pr + nblk;
+    for (int k = 0; k < nblk; ++k) {
+        re += pr[k];
+        im += pi[k];
+    }
+    gW[(p * cout + a) * cin + b] = make_float2((float)re, (float)im);
+}
+
+// ---- spinor (float32 packed) <-> 4-channel features ----------------------------
+__global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh, int nsamples, bool to_features)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= 2ll * Vh * nsamples) return;
+    const int n = (int)(k / (2ll * Vh));
+    const uint32_t idx = (uint32_t)(k - (long long)n * 2 * Vh);
+    const int par = idx >= (uint32_t)Vh ? 1 : 0;
+    const uint32_t cb = idx - (uint32_t)par * Vh;
+    const size_t hb = spinor_site_bytes(P_F32) * (size_t)Vh;
+    char* sp = (char*)spinor + ((size_t)n * 2 + par) * hb;
+    float2* f = feat + (size_t)n * 4 * 2 * 3 * Vh;
+    float v[24];
+    if (to_features) {
+        SpinorIO<P_F32>::load(sp, Vh, cb, v);
+        for (int s = 0; s < 4; ++s)
+            for (int c = 0; c < 3; ++c) f[fidx(s, par, c, Vh, cb)] = make_float2(v[(s * 3 + c) * 2], v[(s * 3 + c) * 2 + 1]);
+    } else {
+        for (int s = 0; s < 4; ++s)
+            for (int c = 0; c < 3; ++c) {
+                const float2 q = f[fidx(s, par, c, Vh, cb)];
+                v[(s * 3 + c) * 2] = q.x;
+                v[(s * 3 + c) * 2 + 1] = q.y;
+            }
+        SpinorIO<P_F32>::store(sp, Vh, cb, v);
+    }
+}
+
+// ---- canonical <-> packed features ----------------------------------------------------
+// canonical: [n][C][T][Z][Y][X][3] complex128
+__global__ void feature_pack_kernel(double* canon, float2* feat, Geom g, int C, long long total, bool unpack)
+{
+    const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= total) return;   // k over (n, c, lex)
+    const long long V = 2ll * g.Vh;
+    const long long nc = k / V;
+    const long long lex = k - nc * V;
+    long long r = lex;
+    const int x = (int)(r % g.L[0]); r /= g.L[0];
+    const int y = (int)(r % g.L[1]); r /= g.L[1];
+    const int z = (int)(r % g.L[2]); r /= g.L[2];
+    const int t = (int)r;
+    const int par = (x + y + z + t) & 1;
+    const uint32_t cb = (uint32_t)(lex >> 1);
+    const int c = (int)(nc % C);
+    const long long n = nc / C;
+    float2* f = feat + (size_t)n * C * 2 * 3 * g.Vh;
+    double* cp = canon + 6 * k;
+    for (int kk = 0; kk < 3; ++kk) {
+        if (unpack) {
+            const float2 q = f[fidx(c, par, kk, g.Vh, cb)];
+            cp[2 * kk] = q.x;
+            cp[2 * kk + 1] = q.y;
+        } else {
+            f[fidx(c, par, kk, g.Vh, cb)] = make_float2((float)cp[2 * kk], (float)cp[2 * kk + 1]);
+        }
+    }
+}
+
+// ---- launchers ---------------------------------------------------------------------------
+template <int R, int WP>
+static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples)
+{
+    dim3 grid((2 * A.g.Vh + 255) / 256, nsamples), block(256);
+    switch (cout) {
+#define WD_PT(C) case C: hipLaunchKernelGGL((ptconv_fwd_kernel<R, C, WP>), grid, block, 0, ctx->stream, A); break;
+        WD_PT(1) WD_PT(2) WD_PT(3) WD_PT(4) WD_PT(8)
+#undef WD_PT
+    default: set_error("ptconv: C_out = %d not in {1, 2, 3, 4, 8}", cout); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+static wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
+                            int nsamples)
+{
+    const void* links;
+    WD_TRY(gauge_links(g, WD_F32, &links));
+    PTArgs A;
+    A.gauge = (const char*)links;
+    A.in = (const float2*)in;
+    A.out = (float2*)out;
+    A.W = W;
+    A.g = g->geom;
+    A.cin = cin;
+    A.in_sample = (long long)cin * 6 * g->geom.Vh;
+    A.out_sample = (long long)cout * 6 * g->geom.Vh;
+    const bool r12 = g->recon == 12;
+    switch (wprec) {
+    case WD_F32: return r12 ? fwd_r_w<12, P_F32>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F32>(g->ctx, A, cout, nsamples);
+    case WD_F16: return r12 ? fwd_r_w<12, P_F16>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F16>(g->ctx, A, cout, nsamples);
+    case WD_BF16: return r12 ? fwd_r_w<12, P_BF16>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_BF16>(g->ctx, A, cout, nsamples);
+    }
+    set_error("ptconv: weight precision %d not in {F32, F16, BF16}", wprec);
+    return WD_EUNSUPPORTED;
+}
+
+static bool ok_channels(int c) { return c == 1 || c == 2 || c == 3 || c == 4 || c == 8; }
+
+template <int R>
+static wd_status wgrad_r(wd_context ctx, const PTArgs& A, int cout, const void* gout, int nsamples, int nblk, double* part)
+{
+    dim3 grid(nblk, 9), block(256);
+    switch (cout) {
+#define WD_PT(C) case C: hipLaunchKernelGGL((ptconv_wgrad_kernel<R, C>), grid, block, 0, ctx->stream, A, (const float2*)gout, nsamples, part); break;
+        WD_PT(1) WD_PT(2) WD_PT(3) WD_PT(4) WD_PT(8)
+#undef WD_PT
+    default: set_error("ptconv: C_out = %d not supported", cout); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+} // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+size_t wd_feature_bytes(const wd_lattice* lat, int channels, int nsamples)
+{
+    Geom g;
+    if (channels < 1 || nsamples < 1 || make_geom(lat, &g) != WD_OK) return 0;
+    return (size_t)nsamples * channels * 2 * 3 * g.Vh * sizeof(float2);
+}
+
+static wd_status feature_io(wd_context ctx, const wd_lattice* lat, int channels, int nsamples, double* canon, void* packed,
+                            bool unpack)
+{
+    Geom g;
+    if (!ctx || !canon || !packed || channels < 1 || nsamples < 1) {
+        set_error("feature pack/unpack: NULL pointer or bad channel/sample count");
+        return WD_EINVAL;
+    }
+    WD_TRY(make_geom(lat, &g));
+    const long long total = (long long)nsamples * channels * 2 * g.Vh;
+    hipLaunchKernelGGL(feature_pack_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, ctx->stream, canon,
+                       (float2*)packed, g, channels, total, unpack);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+wd_status wd_feature_pack(wd_context ctx, const wd_lattice* lat, int channels, int nsamples, const double* canon,
+                          void* packed)
+{
+    return feature_io(ctx, lat, channels, nsamples, (double*)canon, packed, false);
+}
+
+wd_status wd_feature_unpack(wd_context ctx, const wd_lattice* lat, int channels, int nsamples, const void* packed,
+                            double* canon)
+{
+    return feature_io(ctx, lat, channels, nsamples, canon, (void*)packed, true);
+}
+
+wd_status wd_spinor_to_features(wd_context ctx, const wd_lattice* lat, int nsamples, const void* spinor, void* feat)
+{
+    Geom g;
+    if (!ctx || !spinor || !feat || nsamples < 1) {
+        set_error("wd_spinor_to_features: bad argument");
+        return WD_EINVAL;
+    }
+    WD_TRY(make_geom(lat, &g));
+    const long long n = 2ll * g.Vh * nsamples;
+    hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, true);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+wd_status wd_features_to_spinor(wd_context ctx, const wd_lattice* lat, int nsamples, const void* feat, void* spinor)
+{
+    Geom g;
+    if (!ctx || !spinor || !feat || nsamples < 1) {
+        set_error("wd_features_to_spinor: bad argument");
+        return WD_EINVAL;
+    }
+    WD_TRY(make_geom(lat, &g));
+    const long long n = 2ll * g.Vh * nsamples;
+    hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, false);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+wd_status wd_ptconv_forward(wd_gauge g, int cin, int cout, wd_prec wprec, int nsamples, const void* W, const void* in,
+                            void* out)
+{
+    if (!g || !W || !in || !out || nsamples < 1 || nsamples > 65535) {
+        set_error("wd_ptconv_forward: NULL pointer or bad sample count");
+        return WD_EINVAL;
+    }
+    if (!ok_channels(cin) || !ok_channels(cout)) {
+        set_error("wd_ptconv_forward: channels (%d, %d) not in {1, 2, 3, 4, 8}", cin, cout);
+        return WD_EUNSUPPORTED;
+    }
+    if (in == out) {
+        set_error("wd_ptconv_forward: in and out must not alias");
+        return WD_EINVAL;
+    }
+    return ptconv_fwd(g, cin, cout, wprec, W, in, out, nsamples);
+}
+
+wd_status wd_ptconv_backward(wd_gauge g, int cin, int cout, wd_prec wprec, int nsamples, const void* W, const void* in,
+                             const void* gout, void* gin, void* gW)
+{
+    if (!g || !W || !in || !gout || (!gin && !gW) || nsamples < 1 || nsamples > 65535) {
+        set_error("wd_ptconv_backward: NULL pointer or bad sample count");
+        return WD_EINVAL;
+    }
+    if (!ok_channels(cin) || !ok_channels(cout)) {
+        set_error("wd_ptconv_backward: channels (%d, %d) not in {1, 2, 3, 4, 8}", cin, cout);
+        return WD_EUNSUPPORTED;
+    }
+    if (wprec != WD_F32 && wprec != WD_F16 && wprec != WD_BF16) {
+        set_error("wd_ptconv_backward: weight precision %d not supported", (int)wprec);
+        return WD_EUNSUPPORTED;
+    }
+    wd_context ctx = g->ctx;
+    if (gin) {
+        void* Wt;
+        const size_t wbytes = (size_t)9 * cin * cout * (wprec == WD_F32 ? 8 : 4);
+        WD_TRY(ws_get(ctx, "ptconv.Wt", wbytes, &Wt));
+        const int n = 9 * cin * cout;
+        if (wprec == WD_F32)
+            hipLaunchKernelGGL(adjoint_weights_kernel<P_F32>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, W, Wt, cin, cout);
+        else
+            hipLaunchKernelGGL(adjoint_weights_kernel<P_F16>, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, W, Wt, cin, cout);
+        WD_LAUNCHED();
+        WD_TRY(ptconv_fwd(g, cout, cin, wprec, Wt, gout, gin, nsamples));
+    }
+    if (gW) {
+        const void* links;
+        WD_TRY(gauge_links(g, WD_F32, &links));
+        PTArgs A;
+        A.gauge = (const char*)links;
+        A.in = (const float2*)in;
+        A.out = nullptr;
+        A.W = W;
+        A.g = g->geom;
+        A.cin = cin;
+        A.in_sample = (long long)cin * 6 * g->geom.Vh;
+        A.out_sample = (long long)cout * 6 * g->geom.Vh;
+        const long long nsites = 2ll * g->geom.Vh * nsamples;
+        long long nblk = (nsites + 255) / 256;
+        if (nblk > 512) nblk = 512;
+        void* part;
+        WD_TRY(ws_get(ctx, "ptconv.partials", (size_t)9 * cin * 2 * cout * nblk * sizeof(double), &part));
+        WD_TRY(g->recon == 12 ? wgrad_r<12>(ctx, A, cout, gout, nsamples, (int)nblk, (double*)part)
+                              : wgrad_r<18>(ctx, A, cout, gout, nsamples, (int)nblk, (double*)part));
+        const int n = 9 * cin * cout;
+        hipLaunchKernelGGL(wgrad_finish_kernel, dim3((n + 255) / 256), dim3(256), 0, ctx->stream, (const double*)part,
+                           (int)nblk, cin, cout, (float2*)gW);
+        WD_LAUNCHED();
+    }
+    return WD_OK;
+}
+
+} // extern "C"
