@@ -55,7 +55,7 @@ def kernel_source_sha():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(dims):
     """HBM bytes per launch from the committed counter summary, if it was taken
     on the kernel sources as they are now (else None)."""
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "dslash_traffic.json")
@@ -63,7 +63,7 @@ def measured_traffic():
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_src_sha256") != kernel_source_sha() or DIMS != (32, 32, 32, 64):
+    if rec.get("kernel_src_sha256") != kernel_source_sha() or tuple(dims) != (32, 32, 32, 64):
         return None
     return rec.get("bytes_per_launch")
 
@@ -255,7 +255,7 @@ def main():
     bytes_per_launch = Vh * (BYTES_DSLASH + BYTES_XPAY / 2.0)   # averaged over the 4 launches
     achieved = bytes_per_launch / avg_launch_s / 1e9
 
-    traffic = measured_traffic()
+    traffic = measured_traffic(dims)
 
     rec = {
         "metric": "dslash GFLOP/s & %HBM roofline; time to 1e-10 solve, plain vs mixed+learned",

@@ -174,6 +174,8 @@ typedef struct {
     double true_resid;      /* ||b - A x|| / ||b|| in float64, A the solved operator */
     double true_resid_M;    /* ||b - M x|| / ||b|| for wd_wilson_solve, else -1     */
     double seconds;         /* wall time from call to return                      */
+    int cycles;             /* flexible GMRES: restart cycles (float64 residual updates) */
+    int fell_back;          /* flexible GMRES: 1 if it handed over to the plain CG      */
 } wd_solver_info;
 
 /* Solve A x = b, A = M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD), by CG.
@@ -187,6 +189,33 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
  * ||b - M x|| / ||b|| in true_resid_M.  Synchronous. */
 wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
                           const void* b, void* x, wd_solver_info* info);
+
+/* ---- parallel-transport convolution (the learned preconditioner's layer) ----
+ * A feature field holds C colour triplets per site on the whole lattice, in
+ * float32, for nsamples independent samples.  Canonical layout:
+ * [nsamples][C][T][Z][Y][X][3][2] doubles.  One layer maps C_in -> C_out
+ * channels along nine paths p = 0 (stay), 1..4 (+x, +y, +z, +t), 5..8 (-x..-t):
+ *     out^a(x) = sum_p sum_b W[p][a][b] (T_p in^b)(x),
+ *     T_{+mu} f(x) = U_mu(x) s+ f(x + mu),  T_{-mu} f(x) = U_mu(x - mu)^dagger s- f(x - mu),
+ * with the links and boundary signs of the gauge object (float32 links).
+ * W: [9][C_out][C_in] complex, (re, im) pairs at wprec (F32, F16 or BF16).
+ * C_in and C_out must be 1, 2, 3, 4 or 8. */
+size_t wd_feature_bytes(const wd_lattice* lat, int channels, int nsamples);
+wd_status wd_feature_pack(wd_context ctx, const wd_lattice* lat, int channels, int nsamples,
+                          const double* canon, void* packed);
+wd_status wd_feature_unpack(wd_context ctx, const wd_lattice* lat, int channels, int nsamples,
+                            const void* packed, double* canon);
+/* FULL float32 packed spinor <-> 4-channel features (channel = spin). */
+wd_status wd_spinor_to_features(wd_context ctx, const wd_lattice* lat, int nsamples, const void* spinor, void* feat);
+wd_status wd_features_to_spinor(wd_context ctx, const wd_lattice* lat, int nsamples, const void* feat, void* spinor);
+wd_status wd_ptconv_forward(wd_gauge g, int cin, int cout, wd_prec wprec, int nsamples, const void* W,
+                            const void* in, void* out);
+/* Gradients for a real loss L, PyTorch's complex convention (dL/dRe + i dL/dIm):
+ *   gin^b = sum_p T_p^dagger sum_a conj(W[p][a][b]) gout^a            (if gin != NULL)
+ *   gW[p][a][b] = sum_x sum_c gout^a(x)_c conj((T_p in^b)(x)_c)      (if gW != NULL;
+ *                 float32 complex, summed over samples in float64 partials) */
+wd_status wd_ptconv_backward(wd_gauge g, int cin, int cout, wd_prec wprec, int nsamples, const void* W,
+                             const void* in, const void* gout, void* gin, void* gW);
 
 /* ---- batches: many lattices and right-hand sides in one launch --------------- */
 typedef struct {
@@ -214,6 +243,23 @@ wd_status wd_batch_destroy(wd_batch b);
  * lane copy kernel: the achievable-bandwidth ceiling the dslash is compared
  * with, and the reference for hardware byte counters.  Asynchronous. */
 wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t bytes);
+
+/* ---- learned-preconditioner solve ---------------------------------------------- */
+/* Solve M x = b on the full lattice (b, x: FULL float64 packed fields; x is the
+ * initial guess) by flexible GMRES with right preconditioner N, a stack of
+ * nlayers parallel-transport convolutions with channel widths widths[0..nlayers]
+ * (widths[0] = widths[nlayers] = 4: spin as channels) and weights[l] the
+ * [9][widths[l+1]][widths[l]] complex weights at wprec (device pointers);
+ * nlayers = 0 runs unpreconditioned GMRES.  Cycles of at most `restart`
+ * iterations run in float32 and stop when their residual estimate has fallen
+ * by params->delta; x and the true residual b - M x are updated in float64
+ * after each cycle, and the solve ends when ||b - M x|| / ||b|| <= params->tol.
+ * A NaN or a cycle that reduces the true residual less than tenfold hands x
+ * to wd_wilson_solve (fell_back = 1), whose float64 residual is reported.
+ * restart must be in [1, 63].  Synchronous. */
+wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
+                          const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
+                          wd_solver_info* info);
 
 /* ---- launch-shape tuning --------------------------------------------------- */
 /* Time every launch shape of the dslash kernels used with gauge g at precision

@@ -247,8 +247,8 @@ wd_status wd_context_create(int device, void* stream, wd_context* out)
     wd_context c = new wd_context_s();
     c->device = device;
     c->stream = (hipStream_t)stream;
-    if (hipMalloc(&c->dres, 16 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&c->hres, 16 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    if (hipMalloc(&c->dres, 256 * sizeof(double)) != hipSuccess ||
+        hipHostMalloc(&c->hres, 256 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         set_error("wd_context_create: allocation failed");
         if (c->dres) hipFree(c->dres);
         delete c;

@@ -1,0 +1,270 @@
+// Flexible GMRES on the full Wilson system M x = b with a right
+// preconditioner that may change from one iteration to the next (Saad,
+// "A flexible inner-outer preconditioned GMRES algorithm", SISC 1993): here the
+// learned parallel-transport network N ~ M^-1.
+//
+// Mixed precision by iterative refinement: each cycle solves M e = r in
+// float32 (operator, network, Krylov basis) from e = 0 for at most `restart`
+// iterations or until the cycle's residual estimate falls by the factor
+// params->delta; then x += e in float64 and r = b - M x is recomputed in
+// float64, which decides convergence.  Orthogonalisation is classical
+// Gram-Schmidt applied twice (one fused multi-dot and one fused multi-axpy
+// per pass).  The plain solver is the fallback: a NaN, or a cycle that fails
+// to reduce the true residual tenfold, hands x to the even-odd CG
+// (wd_wilson_solve), which then finishes the solve.
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "wd_ops.h"
+
+namespace wd {
+
+typedef std::complex<double> cd;
+
+struct Net {
+    int nlayers;
+    std::vector<int> widths;
+    std::vector<const void*> W;
+    int wprec;
+};
+
+// z = N v on float32 FULL spinor fields (4 channels in and out)
+static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, void* fa, void* fb)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true));
+    void* cur = fa;
+    void* nxt = fb;
+    for (int l = 0; l < net.nlayers; ++l) {
+        WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1));
+        std::swap(cur, nxt);
+    }
+    return launch_spinor_features(ctx, G, 1, z, cur, false);
+}
+
+static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& prm, int m, const Net* net, const void* b,
+                            void* x, wd_solver_info* info, bool* fallback)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    const size_t nh = 2;   // FULL fields
+    const size_t v32 = half_bytes(G, WD_F32) * nh;
+    const size_t v64 = half_bytes(G, WD_F64) * nh;
+    void *V, *Z, *wv, *e, *r, *t, *fa = nullptr, *fb = nullptr;
+    WD_TRY(ws_get(ctx, "fgmres.V", v32 * (m + 1), &V));
+    WD_TRY(ws_get(ctx, "fgmres.Z", v32 * m, &Z));
+    WD_TRY(ws_get(ctx, "fgmres.w", v32, &wv));
+    WD_TRY(ws_get(ctx, "fgmres.e", v32, &e));
+    WD_TRY(ws_get(ctx, "fgmres.r", v64, &r));
+    WD_TRY(ws_get(ctx, "fgmres.t", v64, &t));
+    if (net) {
+        int cmax = 0;
+        for (int c : net->widths) cmax = c > cmax ? c : cmax;
+        const size_t fbytes = (size_t)cmax * 6 * G.Vh * 2 * sizeof(float);
+        WD_TRY(ws_get(ctx, "fgmres.fa", fbytes, &fa));
+        WD_TRY(ws_get(ctx, "fgmres.fb", fbytes, &fb));
+    }
+    auto Vi = [&](int i) { return (void*)((char*)V + (size_t)i * v32); };
+    auto Zi = [&](int i) { return (void*)((char*)Z + (size_t)i * v32); };
+
+    WD_TRY(blas_norm2(ctx, G, nh, WD_F64, b, true));
+    const double bb = ctx->hres[0];
+    const double tol2 = prm.tol * prm.tol * bb;
+    info->iters = 0;
+    info->reliable_updates = 0;
+    info->operator_applies = 0;
+    info->cycles = 0;
+    info->fell_back = 0;
+    *fallback = false;
+    if (!(bb > 0.0)) {
+        WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
+        info->true_resid = info->true_resid_M = 0.0;
+        return WD_OK;
+    }
+    auto true_res = [&](double* rr) -> wd_status {
+        WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
+        WD_TRY(blas_xmy_norm(ctx, G, nh, b, t, r, true));
+        *rr = ctx->hres[0];
+        info->operator_applies++;
+        return WD_OK;
+    };
+    double rr;
+    WD_TRY(true_res(&rr));
+    const double inner = prm.delta > 0.0 ? prm.delta : 1e-4;
+    while (rr > tol2 && info->iters < prm.maxiter) {
+        // ---- one float32 cycle on M e = r -----------------------------------------
+        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, WD_F32, Vi(0)));
+        WD_TRY(blas_norm2(ctx, G, nh, WD_F32, Vi(0), true));
+        const double beta = std::sqrt(ctx->hres[0]);
+        if (!std::isfinite(beta) || beta == 0.0) {
+            *fallback = !std::isfinite(beta);
+            break;
+        }
+        WD_TRY(blas_axpby(ctx, G, nh, WD_F32, Vi(0), 0.0, WD_F32, Vi(0), 1.0 / beta));
+        std::vector<std::vector<cd>> H(m + 1, std::vector<cd>(m, 0.0));
+        std::vector<cd> gvec(m + 1, 0.0), cs(m), sn(m);
+        gvec[0] = beta;
+        int j = 0;
+        bool bad = false;
+        for (; j < m && info->iters < prm.maxiter; ++j) {
+            if (net) WD_TRY(apply_net(g, *net, Vi(j), Zi(j), fa, fb));
+            else WD_TRY(launch_convert(ctx, G, nh, WD_F32, Vi(j), WD_F32, Zi(j)));
+            WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F32, 1, Zi(j), wv));
+            info->operator_applies++;
+            info->iters++;
+            for (int pass = 0; pass < 2; ++pass) {
+                WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true));
+                std::vector<double> coef(2 * (j + 1));
+                for (int i = 0; i <= j; ++i) {
+                    const cd h(ctx->hres[2 * i], ctx->hres[2 * i + 1]);
+                    H[i][j] += h;
+                    coef[2 * i] = -h.real();
+                    coef[2 * i + 1] = -h.imag();
+                }
+                WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, V, v32, j + 1, coef.data(), wv));
+            }
+            WD_TRY(blas_norm2(ctx, G, nh, WD_F32, wv, true));
+            const double hn = std::sqrt(ctx->hres[0]);
+            if (!std::isfinite(hn)) {
+                bad = true;
+                break;
+            }
+            H[j + 1][j] = hn;
+            // apply the previous rotations to column j, then make a new one
+            for (int i = 0; i < j; ++i) {
+                const cd a = H[i][j], c = H[i + 1][j];
+                H[i][j] = std::conj(cs[i]) * a + std::conj(sn[i]) * c;
+                H[i + 1][j] = -sn[i] * a + cs[i] * c;
+            }
+            const cd a = H[j][j], c = H[j + 1][j];
+            const double den = std::sqrt(std::norm(a) + std::norm(c));
+            if (den == 0.0) {
+                bad = true;
+                break;
+            }
+            cs[j] = a / den;
+            sn[j] = c / den;
+            H[j][j] = std::conj(cs[j]) * a + std::conj(sn[j]) * c;
+            H[j + 1][j] = 0.0;
+            gvec[j + 1] = -sn[j] * gvec[j];
+            gvec[j] = std::conj(cs[j]) * gvec[j];
+            if (hn > 0.0) {
+                WD_TRY(launch_convert(ctx, G, nh, WD_F32, wv, WD_F32, Vi(j + 1)));
+                WD_TRY(blas_axpby(ctx, G, nh, WD_F32, Vi(j + 1), 1.0 / hn, WD_F32, Vi(j + 1), 0.0));
+            }
+            if (std::abs(gvec[j + 1]) <= inner * beta || hn == 0.0) {
+                ++j;
+                break;
+            }
+        }
+        if (bad) {
+            *fallback = true;
+            break;
+        }
+        // y = H^-1 g (upper triangular, j x j); e = sum y_i Z_i; x += e
+        std::vector<cd> y(j);
+        for (int i = j - 1; i >= 0; --i) {
+            cd s = gvec[i];
+            for (int k = i + 1; k < j; ++k) s -= H[i][k] * y[k];
+            y[i] = s / H[i][i];
+        }
+        std::vector<double> coef(2 * j);
+        bool finite = true;
+        for (int i = 0; i < j; ++i) {
+            coef[2 * i] = y[i].real();
+            coef[2 * i + 1] = y[i].imag();
+            finite = finite && std::isfinite(coef[2 * i]) && std::isfinite(coef[2 * i + 1]);
+        }
+        if (!finite) {
+            *fallback = true;
+            break;
+        }
+        WD_TRY(blas_zero(ctx, G, nh, WD_F32, e));
+        for (int i0 = 0; i0 < j; i0 += WD_MAXPY) {
+            const int k = j - i0 < WD_MAXPY ? j - i0 : WD_MAXPY;
+            WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, Zi(i0), v32, k, coef.data() + 2 * i0, e));
+        }
+        WD_TRY(blas_axpby(ctx, G, nh, WD_F32, e, 1.0, WD_F64, x, 1.0));
+        const double rr_prev = rr;
+        WD_TRY(true_res(&rr));
+        info->reliable_updates++;
+        info->cycles++;
+        if (!std::isfinite(rr) || (rr > 0.01 * rr_prev && rr > tol2)) {   // NaN, or less than 10x per cycle
+            *fallback = true;
+            break;
+        }
+    }
+    info->true_resid = info->true_resid_M = std::sqrt(rr / bb);
+    if (*fallback) return WD_OK;
+    return rr <= tol2 ? WD_OK : WD_ENOCONV;
+}
+
+} // namespace wd
+
+using namespace wd;
+
+extern "C" {
+
+wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
+                          const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
+                          wd_solver_info* info)
+{
+    if (!g || !params || !b || !x || !info || restart < 1 || restart > WD_MAXPY - 1 || nlayers < 0 ||
+        (nlayers > 0 && (!widths || !weights))) {
+        set_error("wd_fgmres_solve: bad argument");
+        return WD_EINVAL;
+    }
+    if (!(params->tol > 0.0) || params->maxiter < 0) {
+        set_error("wd_fgmres_solve: bad tolerance or maxiter");
+        return WD_EINVAL;
+    }
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    Net net;
+    if (nlayers > 0) {
+        if (widths[0] != 4 || widths[nlayers] != 4) {
+            set_error("wd_fgmres_solve: the network must map 4 channels (spin) to 4 channels");
+            return WD_EINVAL;
+        }
+        net.nlayers = nlayers;
+        net.widths.assign(widths, widths + nlayers + 1);
+        net.W.assign(weights, weights + nlayers);
+        net.wprec = wprec;
+        for (int l = 0; l < nlayers; ++l) {
+            const int c = widths[l + 1];
+            if (!(c == 1 || c == 2 || c == 3 || c == 4 || c == 8) || !weights[l]) {
+                set_error("wd_fgmres_solve: layer %d: width %d unsupported or weights NULL", l, c);
+                return WD_EUNSUPPORTED;
+            }
+        }
+    }
+    WD_HIP(hipStreamSynchronize(g->ctx->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    bool fallback = false;
+    wd_status s = fgmres_run(g, kappa, *params, restart, nlayers > 0 ? &net : nullptr, b, x, info, &fallback);
+    if (s == WD_OK && fallback) {
+        // hand the current iterate to the plain solver, which also judges the final residual
+        wd_solver_info ci{};
+        const int done = info->iters;
+        wd_solver_params p2 = *params;
+        p2.maxiter = params->maxiter - done > 0 ? params->maxiter - done : 1;
+        if (p2.delta <= 0.0 || p2.delta >= 1.0) p2.delta = 0.1;
+        if (p2.sloppy == WD_F64 || p2.sloppy > WD_BF16) p2.sloppy = WD_F32;
+        s = wd_wilson_solve(g, kappa, &p2, b, x, &ci);
+        info->iters += ci.iters;
+        info->operator_applies += ci.operator_applies;
+        info->true_resid = info->true_resid_M = ci.true_resid_M;
+        info->reliable_updates += ci.reliable_updates;
+        info->fell_back = 1;
+    }
+    info->status = s;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}
+
+} // extern "C"

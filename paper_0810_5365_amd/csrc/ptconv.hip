@@ -346,7 +346,7 @@ static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples
     return WD_OK;
 }
 
-static wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
+wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
                             int nsamples)
 {
     const void* links;
@@ -368,6 +368,16 @@ static wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void
     }
     set_error("ptconv: weight precision %d not in {F32, F16, BF16}", wprec);
     return WD_EUNSUPPORTED;
+}
+
+wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, void* spinor, void* feat,
+                                 bool to_features)
+{
+    const long long n = 2ll * g.Vh * nsamples;
+    hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
+                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, to_features);
+    WD_LAUNCHED();
+    return WD_OK;
 }
 
 static bool ok_channels(int c) { return c == 1 || c == 2 || c == 3 || c == 4 || c == 8; }
@@ -435,11 +445,7 @@ wd_status wd_spinor_to_features(wd_context ctx, const wd_lattice* lat, int nsamp
         return WD_EINVAL;
     }
     WD_TRY(make_geom(lat, &g));
-    const long long n = 2ll * g.Vh * nsamples;
-    hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
-                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, true);
-    WD_LAUNCHED();
-    return WD_OK;
+    return launch_spinor_features(ctx, g, nsamples, (void*)spinor, feat, true);
 }
 
 wd_status wd_features_to_spinor(wd_context ctx, const wd_lattice* lat, int nsamples, const void* feat, void* spinor)
@@ -450,11 +456,7 @@ wd_status wd_features_to_spinor(wd_context ctx, const wd_lattice* lat, int nsamp
         return WD_EINVAL;
     }
     WD_TRY(make_geom(lat, &g));
-    const long long n = 2ll * g.Vh * nsamples;
-    hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
-                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, false);
-    WD_LAUNCHED();
-    return WD_OK;
+    return launch_spinor_features(ctx, g, nsamples, spinor, (void*)feat, false);
 }
 
 wd_status wd_ptconv_forward(wd_gauge g, int cin, int cout, wd_prec wprec, int nsamples, const void* W, const void* in,

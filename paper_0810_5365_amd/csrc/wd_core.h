@@ -133,5 +133,17 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
+// h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[2i], dres[2i + 1]
+wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
+                    const void* w, bool fetch);
+// w += sum_i c_i V_i, complex c_i = (coef[2i], coef[2i + 1]), i < k <= WD_MAXPY
+constexpr int WD_MAXPY = 64;
+wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
+                     const double* coef, void* w);
+
+// ---- ptconv.hip ----------------------------------------------------------------
+wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples);
+wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, void* spinor, void* feat,
+                                 bool to_features);
 
 } // namespace wd

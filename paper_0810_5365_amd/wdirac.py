@@ -39,7 +39,7 @@ class WdSolverParams(ctypes.Structure):
 class WdSolverInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("operator_applies", ctypes.c_int),
                 ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("true_resid_M", ctypes.c_double),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("cycles", ctypes.c_int), ("fell_back", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -84,11 +84,19 @@ _PROTOS = {
     "wd_caxpy": ("status", [_V, _P(WdLattice), _I, _I, _I, _D, _D, _V, _V]),
     "wd_cg_solve": ("status", [_V, _D, _I, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
     "wd_wilson_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
+    "wd_feature_bytes": (_S, [_P(WdLattice), _I, _I]),
+    "wd_feature_pack": ("status", [_V, _P(WdLattice), _I, _I, _V, _V]),
+    "wd_feature_unpack": ("status", [_V, _P(WdLattice), _I, _I, _V, _V]),
+    "wd_spinor_to_features": ("status", [_V, _P(WdLattice), _I, _V, _V]),
+    "wd_features_to_spinor": ("status", [_V, _P(WdLattice), _I, _V, _V]),
+    "wd_ptconv_forward": ("status", [_V, _I, _I, _I, _I, _V, _V, _V]),
+    "wd_ptconv_backward": ("status", [_V, _I, _I, _I, _I, _V, _V, _V, _V, _V]),
     "wd_batch_create": ("status", [_V, _I, _P(WdBatchItem), _I, _P(_V)]),
     "wd_batch_run": ("status", [_V]),
     "wd_batch_info": ("status", [_V, _P(ctypes.c_longlong), _P(_I)]),
     "wd_batch_destroy": ("status", [_V]),
     "wd_device_copy": ("status", [_V, _V, _V, _S]),
+    "wd_fgmres_solve": ("status", [_V, _D, _P(WdSolverParams), _I, _I, _P(_I), _P(_V), _I, _V, _V, _P(WdSolverInfo)]),
     "wd_autotune_dslash": ("status", [_V, _I, _I, ctypes.c_char_p]),
     "wd_tune_save": ("status", [_V, ctypes.c_char_p]),
     "wd_tune_load": ("status", [_V, ctypes.c_char_p]),
@@ -187,6 +195,7 @@ class Gauge:
         self.bc = tuple(bc)
         self.lat = lattice(dims, bc)
         self.recon = recon
+        self.geom_vh = int(np.prod(self.dims)) // 2
         h = ctypes.c_void_p()
         wd_gauge_create(ctx.handle, ctypes.byref(self.lat), int(recon), ctypes.byref(h))
         self.handle = h
@@ -254,6 +263,28 @@ def unpack(ctx, lat, subset, prec, packed, shape, nrhs=1):
     canon = torch.empty(n, dtype=torch.float64, device="cuda:%d" % ctx.device)
     wd_spinor_unpack(ctx.handle, ctypes.byref(lat), int(subset), int(prec), int(nrhs), ctypes.c_void_p(packed.data_ptr()),
                      ctypes.c_void_p(canon.data_ptr()))
+    torch.cuda.current_stream(ctx.device).synchronize()
+    return canon.cpu().numpy().view(np.complex128).reshape(shape)
+
+
+def feature_bytes(lat, channels, nsamples=1):
+    return int(wd_feature_bytes(ctypes.byref(lat), int(channels), int(nsamples)))
+
+
+def pack_features(ctx, lat, canon, channels, nsamples=1):
+    """canonical complex (nsamples, C, T, Z, Y, X, 3) on the host -> packed float32 device features."""
+    import torch
+    c = torch.from_numpy(np.ascontiguousarray(canon, dtype=np.complex128).view(np.float64)).to("cuda:%d" % ctx.device)
+    out = torch.empty(feature_bytes(lat, channels, nsamples) // 4, dtype=torch.float32, device="cuda:%d" % ctx.device)
+    wd_feature_pack(ctx.handle, ctypes.byref(lat), int(channels), int(nsamples), c.data_ptr(), out.data_ptr())
+    return out
+
+
+def unpack_features(ctx, lat, packed, shape, channels, nsamples=1):
+    import torch
+    n = int(np.prod(shape)) * 2
+    canon = torch.empty(n, dtype=torch.float64, device="cuda:%d" % ctx.device)
+    wd_feature_unpack(ctx.handle, ctypes.byref(lat), int(channels), int(nsamples), packed.data_ptr(), canon.data_ptr())
     torch.cuda.current_stream(ctx.device).synchronize()
     return canon.cpu().numpy().view(np.complex128).reshape(shape)
 
