@@ -264,8 +264,9 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
 /* ---- launch-shape tuning --------------------------------------------------- */
 /* Time every launch shape of the dslash kernels used with gauge g at precision
  * prec and nrhs right-hand sides (workgroup size 64..256, XCD-aware block
- * remap, non-temporal link loads, software-pipelined directions and, for
- * nrhs > 1, right-hand sides interleaved with the site tiles), for both
+ * remap, non-temporal link loads, software-pipelined directions, a z-blocked
+ * site traversal of depth zb dividing Z and, for nrhs > 1, right-hand sides
+ * interleaved with the site tiles), for both
  * dagger settings with and without the fused a x + b D in, and keep the
  * fastest in the context's tuning table.  If cache_path is not NULL the file
  * is read first and the whole table written back after.  Synchronous; uses
@@ -274,9 +275,9 @@ wd_status wd_autotune_dslash(wd_gauge g, wd_prec prec, int nrhs, const char* cac
 /* Write / read the tuning table as JSON (a missing file reads as empty). */
 wd_status wd_tune_save(wd_context ctx, const char* path);
 wd_status wd_tune_load(wd_context ctx, const char* path);
-/* Look up one tuning entry by key; fills out5 = {block, remap, nt, pf,
- * rhs_inner} and returns 1, or returns 0 if the key is absent. */
-int wd_tune_get(wd_context ctx, const char* key, int* out5);
+/* Look up one tuning entry by key; fills out6 = {block, remap, nt, pf,
+ * rhs_inner, zb} and returns 1, or returns 0 if the key is absent. */
+int wd_tune_get(wd_context ctx, const char* key, int* out6);
 
 #ifdef __cplusplus
 }

@@ -109,6 +109,7 @@ TuneParam tune_lookup(wd_context ctx, const std::string& key)
     if (const char* e = getenv("WD_DSLASH_NT")) tp.nt = atoi(e);
     if (const char* e = getenv("WD_DSLASH_PF")) tp.pf = atoi(e);
     if (const char* e = getenv("WD_DSLASH_RHS_INNER")) tp.rhs_inner = atoi(e);
+    if (const char* e = getenv("WD_DSLASH_ZB")) tp.zb = atoi(e);
     return tp;
 }
 

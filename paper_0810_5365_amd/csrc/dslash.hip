@@ -16,9 +16,15 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs A)
         rhs = (int)(bid % (uint32_t)A.rhs_inner);
         bid /= (uint32_t)A.rhs_inner;
     }
-    const uint32_t cb = bid * blockDim.x + threadIdx.x;
-    if (cb >= (uint32_t)A.g.Vh) return;
-    dslash_site<P, R, DAG, XPAY, NT, PF>(A, cb, rhs);
+    const uint32_t i = bid * blockDim.x + threadIdx.x;
+    if (i >= (uint32_t)A.g.Vh) return;
+    if (A.zb > 0) {
+        int c[4];
+        const uint32_t cb = zblock_site(A, i, c);
+        dslash_site<P, R, DAG, XPAY, NT, PF>(A, cb, c, rhs);
+    } else {
+        dslash_site<P, R, DAG, XPAY, NT, PF>(A, i, rhs);
+    }
 }
 
 template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
@@ -65,6 +71,12 @@ wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c
     A.par = c.par;
     A.remap = tp.remap;
     A.rhs_inner = (tp.rhs_inner && c.nrhs > 1) ? c.nrhs : 0;
+    A.zb = 0;
+    if (tp.zb > 0 && tp.zb < g.L[2] && g.L[2] % tp.zb == 0) {
+        A.zb = tp.zb;
+        A.dzb = make_fastdiv((uint32_t)tp.zb);
+        A.dt = make_fastdiv((uint32_t)g.L[3]);
+    }
     if ((long long)((g.Vh + tp.block - 1) / tp.block) * c.nrhs >= (1ll << 31)) A.rhs_inner = 0;
     const bool r12 = c.recon == 12;
     switch (c.prec) {

@@ -38,7 +38,32 @@ struct DslashArgs {
     int par;
     int remap;
     int rhs_inner;   // > 1: that many rhs interleaved with the site tiles on grid x
+    int zb;          // > 0: z-blocked site traversal with this block depth (divides Z)
+    FastDiv dzb, dt; // division by zb and by T for the blocked traversal
 };
+
+// Site order index i -> checkerboard index and coordinates of the z-blocked
+// traversal: i = xh + Xh (y + Y (zi + zb (t + T b))), z = b zb + zi.  Sites of
+// one z-block are walked through all t before the next block, so the slices
+// t - 1, t, t + 1 of a block that the stencil reads stay close in time.
+__device__ __forceinline__ uint32_t zblock_site(const DslashArgs& A, uint32_t i, int c[4])
+{
+    const Geom& g = A.g;
+    const uint32_t q1 = fdiv(i, g.dxh);
+    const uint32_t xh = i - q1 * (uint32_t)g.Xh;
+    const uint32_t q2 = fdiv(q1, g.dy);
+    const uint32_t y = q1 - q2 * (uint32_t)g.L[1];
+    const uint32_t q3 = fdiv(q2, A.dzb);
+    const uint32_t zi = q2 - q3 * (uint32_t)A.zb;
+    const uint32_t b = fdiv(q3, A.dt);
+    const uint32_t t = q3 - b * (uint32_t)g.L[3];
+    const uint32_t z = b * (uint32_t)A.zb + zi;
+    c[1] = (int)y;
+    c[2] = (int)z;
+    c[3] = (int)t;
+    c[0] = (int)(2 * xh + ((A.par + y + z + t) & 1));
+    return xh + (uint32_t)g.Xh * (y + (uint32_t)g.L[1] * (z + (uint32_t)g.L[2] * t));
+}
 
 // Loads of direction D: the link (U_mu(x) forward, U_mu(x - mu) backward)
 // and the neighbour spinor.
@@ -99,11 +124,9 @@ __device__ __forceinline__ void hop_pipelined(const DslashArgs& A, uint32_t cb, 
 }
 
 template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
-__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs)
+__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, const int c[4], int rhs)
 {
     using T = typename RealOf<P>::T;
-    int c[4];
-    cb_coords(A.g, cb, A.par, c);
     const size_t gbytes = link_site_bytes(P, R) * (size_t)A.g.Vh;
     const char* in = A.in + rhs * A.in_stride;
     T acc[24];
@@ -142,6 +165,14 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, in
         for (int k = 0; k < 24; ++k) acc[k] *= b;
     }
     SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.Vh, cb, acc);
+}
+
+template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
+__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs)
+{
+    int c[4];
+    cb_coords(A.g, cb, A.par, c);
+    dslash_site<P, R, DAG, XPAY, NT, PF>(A, cb, c, rhs);
 }
 
 } // namespace wd

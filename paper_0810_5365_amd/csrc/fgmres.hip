@@ -14,6 +14,7 @@
 // (wd_wilson_solve), which then finishes the solve.
 #include <chrono>
 #include <cmath>
+#include <algorithm>
 #include <complex>
 #include <vector>
 
@@ -96,6 +97,8 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     const double inner = prm.delta > 0.0 ? prm.delta : 1e-4;
     while (rr > tol2 && info->iters < prm.maxiter) {
         // ---- one float32 cycle on M e = r -----------------------------------------
+        // stop the cycle at delta, or earlier if that already meets the requested tolerance
+        const double cycle_tol = std::max(inner, 0.5 * std::sqrt(tol2 / rr));
         WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, WD_F32, Vi(0)));
         WD_TRY(blas_norm2(ctx, G, nh, WD_F32, Vi(0), true));
         const double beta = std::sqrt(ctx->hres[0]);
@@ -155,7 +158,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
                 WD_TRY(launch_convert(ctx, G, nh, WD_F32, wv, WD_F32, Vi(j + 1)));
                 WD_TRY(blas_axpby(ctx, G, nh, WD_F32, Vi(j + 1), 1.0 / hn, WD_F32, Vi(j + 1), 0.0));
             }
-            if (std::abs(gvec[j + 1]) <= inner * beta || hn == 0.0) {
+            if (std::abs(gvec[j + 1]) <= cycle_tol * beta || hn == 0.0) {
                 ++j;
                 break;
             }

@@ -49,9 +49,9 @@ wd_status tune_save(wd_context ctx, const char* path)
     fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
     size_t i = 0;
     for (auto& kv : ctx->tune) {
-        fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d, \"ri\": %d}%s\n",
+        fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d, \"ri\": %d, \"zb\": %d}%s\n",
                 kv.first.c_str(), kv.second.block, kv.second.remap, kv.second.nt, kv.second.pf, kv.second.rhs_inner,
-                ++i < ctx->tune.size() ? "," : "");
+                kv.second.zb, ++i < ctx->tune.size() ? "," : "");
     }
     fprintf(f, "]}\n");
     fclose(f);
@@ -72,6 +72,8 @@ wd_status tune_load(wd_context ctx, const char* path)
                    &tp.remap, &tp.nt, &tp.pf) == 5) {
             const char* ri = strstr(p, "\"ri\": ");
             if (ri) tp.rhs_inner = atoi(ri + 6);
+            const char* zb = strstr(p, "\"zb\": ");
+            if (zb) tp.zb = atoi(zb + 6);
             if (tp.block >= 64 && tp.block <= 256 && tp.block % 64 == 0) ctx->tune[key] = tp;
         }
     }
@@ -113,6 +115,10 @@ wd_status autotune_dslash(wd_gauge g, int prec, int nrhs, int* ntuned)
             c.recon = g->recon;
             TuneParam best;
             float best_us = 1e30f;
+            std::vector<int> zbs{0};
+            for (int d = 2; d < G.L[2]; d *= 2)
+                if (G.L[2] % d == 0) zbs.push_back(d);
+            for (int zb : zbs)
             for (int block = 64; block <= 256; block += 64)
                 for (int remap = 0; remap < 2; ++remap)
                     for (int nt = 0; nt < 2; ++nt)
@@ -124,6 +130,7 @@ wd_status autotune_dslash(wd_gauge g, int prec, int nrhs, int* ntuned)
                             tp.nt = nt;
                             tp.pf = pf;
                             tp.rhs_inner = ri;
+                            tp.zb = zb;
                             float us;
                             WD_TRY(time_launch(ctx, G, c, tp, reps, &us));
                             if (us < best_us) {
@@ -178,16 +185,17 @@ wd_status wd_tune_load(wd_context ctx, const char* path)
     return tune_load(ctx, path);
 }
 
-int wd_tune_get(wd_context ctx, const char* key, int* out5)
+int wd_tune_get(wd_context ctx, const char* key, int* out6)
 {
-    if (!ctx || !key || !out5) return 0;
+    if (!ctx || !key || !out6) return 0;
     auto it = ctx->tune.find(key);
     if (it == ctx->tune.end()) return 0;
-    out5[0] = it->second.block;
-    out5[1] = it->second.remap;
-    out5[2] = it->second.nt;
-    out5[3] = it->second.pf;
-    out5[4] = it->second.rhs_inner;
+    out6[0] = it->second.block;
+    out6[1] = it->second.remap;
+    out6[2] = it->second.nt;
+    out6[3] = it->second.pf;
+    out6[4] = it->second.rhs_inner;
+    out6[5] = it->second.zb;
     return 1;
 }
 

@@ -48,6 +48,7 @@ struct TuneParam {
     int nt = 0;   // non-temporal link loads
     int pf = 0;   // software-pipelined directions
     int rhs_inner = 1;   // several rhs: interleave them with the site tiles
+    int zb = 0;          // z-blocked site traversal depth (0: natural order)
 };
 
 inline bool valid_prec(int p) { return p >= WD_F64 && p <= WD_BF16; }

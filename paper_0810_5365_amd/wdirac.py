@@ -295,9 +295,9 @@ def dslash_key(dims, prec, recon, nrhs, dagger, xpay):
 
 
 def tune_get(ctx, key):
-    out = (ctypes.c_int * 5)()
+    out = (ctypes.c_int * 6)()
     if wd_tune_get(ctx.handle, key.encode(), out):
-        return {"block": out[0], "remap": out[1], "nt": out[2], "pf": out[3], "rhs_inner": out[4]}
+        return {"block": out[0], "remap": out[1], "nt": out[2], "pf": out[3], "rhs_inner": out[4], "zb": out[5]}
     return None
 
 

@@ -1,0 +1,108 @@
+"""GPU: flexible GMRES with and without the network preconditioner reaches the
+requested residual (recomputed by the FP64 oracle), the fallback to the plain
+solver fires on a broken network, and training lowers the loss."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import lattice_synth as ls
+import oracle as orc
+
+pytestmark = pytest.mark.gpu
+BC = (1, 1, 1, -1)
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_0810_5365_amd import wdirac as w
+    ctx = w.Context(0)
+    dims = (8, 8, 8, 16)
+    U = ls.gauge_field(dims, 0.7, 5001)
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(U)
+    yield w, ctx, dims, U, g
+    g.close()
+    ctx.close()
+
+
+def _solve(w, ctx, g, dims, kappa, net_ws=None, widths=None, wprec=0, restart=16, tol=1e-10):
+    import torch
+    lat = w.lattice(dims, BC)
+    X, Y, Z, T = dims
+    b = ls.gaussian_complex((T, Z, Y, X, 4, 3), 9, ls.STREAM_SPINOR)
+    fb = w.pack(ctx, lat, w.FULL, w.F64, b)
+    fx = torch.zeros_like(fb)
+    prm = w.solver_params(tol=tol, maxiter=3000, sloppy=w.F32, delta=1e-4)
+    info = w.WdSolverInfo()
+    if net_ws is None:
+        w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), restart, 0, None, None, w.F32, fb.data_ptr(),
+                          fx.data_ptr(), ctypes.byref(info))
+    else:
+        wid = (ctypes.c_int * len(widths))(*widths)
+        ptrs = (ctypes.c_void_p * len(net_ws))(*[t.data_ptr() for t in net_ws])
+        w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), restart, len(net_ws), wid, ptrs, wprec, fb.data_ptr(),
+                          fx.data_ptr(), ctypes.byref(info))
+    x = w.unpack(ctx, lat, w.FULL, w.F64, fx, b.shape)
+    return info, orc.rel_residual(lambda v: orc.apply_m(orc_links(dims), v, kappa, BC), x, b)
+
+
+_LINKS = {}
+
+
+def orc_links(dims):
+    return _LINKS[dims]
+
+
+def test_fgmres_unpreconditioned(env):
+    w, ctx, dims, U, g = env
+    _LINKS[dims] = U
+    info, res = _solve(w, ctx, g, dims, 0.1248)
+    assert info.status == w.WD_OK and info.fell_back == 0
+    assert res <= 1.05e-10, (res, info.as_dict())
+    assert abs(res - info.true_resid_M) < 1e-12
+
+
+@pytest.mark.parametrize("wprec", ["f32", "bf16"])
+def test_fgmres_with_network(env, wprec):
+    import torch
+    from paper_0810_5365_amd import ptconv as pt
+    w, ctx, dims, U, g = env
+    _LINKS[dims] = U
+    net = pt.PTNet((4, 8, 8, 4), w.PREC_BY_NAME[wprec])
+    net.init_identity(hop=0.02)
+    info, res = _solve(w, ctx, g, dims, 0.1248, net.storage(), net.widths, net.wprec)
+    assert info.status == w.WD_OK
+    assert res <= 1.05e-10, (res, info.as_dict())
+
+
+def test_fgmres_falls_back_on_a_broken_network(env):
+    import torch
+    from paper_0810_5365_amd import ptconv as pt
+    w, ctx, dims, U, g = env
+    _LINKS[dims] = U
+    net = pt.PTNet((4, 4), w.F32)
+    with torch.no_grad():
+        net.weights[0].fill_(float("nan"))
+    info, res = _solve(w, ctx, g, dims, 0.1248, net.storage(), net.widths, net.wprec)
+    assert info.fell_back == 1 and info.status == w.WD_OK
+    assert res <= 1.05e-10
+
+
+def test_training_lowers_the_loss():
+    import torch
+    from paper_0810_5365_amd import wdirac as w, ptconv as pt, learn
+    ctx = w.Context(0)
+    kappa = 0.1248
+    fields = [learn.Field(ctx, (4, 4, 4, 8), 0.7, s) for s in (11, 12)]
+    net = pt.PTNet((4, 8, 8, 4), w.F32)
+    net.init_identity()
+    before = learn.evaluate_loss(net, fields, kappa, n=4)
+    hist = learn.train(net, fields, kappa, pairs_per_field=64, batch=4, epochs=2, lr=3e-3, n_null=4)
+    after = learn.evaluate_loss(net, fields, kappa, n=4)
+    assert np.all(np.isfinite(hist["loss"]))
+    assert after < 0.7 * before, (before, after)
+    for f in fields:
+        f.close()
+    ctx.close()

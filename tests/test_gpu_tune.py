@@ -26,7 +26,7 @@ def test_autotune_then_parity_and_cache_roundtrip(tmp_path):
     for dag in (0, 1):
         for xp in (0, 1):
             e = w.tune_get(ctx, w.dslash_key(dims, w.F32, 12, 1, dag, xp))
-            assert e is not None and e["block"] in (64, 128, 192, 256)
+            assert e is not None and e["block"] in (64, 128, 192, 256) and e["zb"] in (0, 2, 4)
             entries[(dag, xp)] = e
     assert os.path.exists(path) and '"entries"' in open(path).read()
     lat = w.lattice(dims, BC)
@@ -47,14 +47,16 @@ def test_autotune_then_parity_and_cache_roundtrip(tmp_path):
     ctx2.close()
 
 
-@pytest.mark.parametrize("block,remap,nt,pf", [(64, 0, 0, 0), (128, 1, 1, 0), (192, 1, 0, 1), (256, 0, 1, 1)])
-def test_every_launch_shape_is_correct(block, remap, nt, pf, monkeypatch):
+@pytest.mark.parametrize("block,remap,nt,pf,zb", [(64, 0, 0, 0, 0), (128, 1, 1, 0, 2), (192, 1, 0, 1, 5),
+                                                   (256, 0, 1, 1, 0), (64, 1, 1, 1, 2)])
+def test_every_launch_shape_is_correct(block, remap, nt, pf, zb, monkeypatch):
     """Each shape the tuner may pick gives the oracle's result (set through the
     environment defaults that apply when the table has no entry)."""
     monkeypatch.setenv("WD_DSLASH_BLOCK", str(block))
     monkeypatch.setenv("WD_DSLASH_REMAP", str(remap))
     monkeypatch.setenv("WD_DSLASH_NT", str(nt))
     monkeypatch.setenv("WD_DSLASH_PF", str(pf))
+    monkeypatch.setenv("WD_DSLASH_ZB", str(zb))
     from paper_0810_5365_amd import wdirac as w
     dims = (6, 4, 10, 4)
     X, Y, Z, T = dims
