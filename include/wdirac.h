@@ -111,6 +111,13 @@ wd_status wd_gauge_prepare(wd_gauge g, wd_prec prec);
 /* Bytes of packed device link storage at precision `prec` (0 on bad input). */
 size_t wd_gauge_bytes(wd_gauge g, wd_prec prec);
 wd_status wd_gauge_destroy(wd_gauge g);
+/* Temporal gauge fixing (paper, Sections 4 and 7): rotate the uploaded links
+ * by Omega(x, 0) = 1, Omega(x, t + 1) = Omega(x, t) U_t(x, t), so that every
+ * t-link is exactly the identity except on the last time slice; from then on
+ * the dslash skips those links.  Solutions in the fixed gauge are Omega x.
+ * omega_out (host, may be NULL) receives Omega as [T][Z][Y][X][3][3][2].
+ * A later wd_gauge_upload clears the fixed state.  Synchronous. */
+wd_status wd_gauge_fix_temporal(wd_gauge g, double* omega_out);
 
 /* ---- spinor fields (paper, Section 5: 24 floats per site, split by parity,
  *      stored as structure-of-arrays of 16-byte vectors) ---------------------- */

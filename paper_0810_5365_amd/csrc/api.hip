@@ -163,6 +163,7 @@ wd_status hop_half(wd_gauge g, int prec, int par, int dagger, int nrhs, const vo
     c.dagger = dagger;
     c.prec = prec;
     c.recon = g->recon;
+    c.gf = g->gf ? 1 : 0;
     return launch_dslash(g->ctx, g->geom, c);
 }
 
@@ -331,6 +332,7 @@ wd_status wd_gauge_upload(wd_gauge g, const double* links, int on_device)
                           g->ctx->stream));
     WD_HIP(hipStreamSynchronize(g->ctx->stream));
     g->uploaded = true;
+    g->gf = false;
     // repack every precision already in use
     for (int p = 0; p < 4; ++p)
         if (g->packed[p]) WD_TRY(launch_pack_gauge(g->ctx, g->geom, p, g->recon, g->canon, g->packed[p]));

@@ -143,6 +143,7 @@ wd_status wd_batch_create(wd_context ctx, int n, const wd_batch_item* items, wd_
         B.A.remap = 0;
         B.A.rhs_inner = 0;
         B.A.zb = 0;
+        B.A.gf = it.gauge->gf ? 1 : 0;
         B.dagger = it.dagger != 0;
         B.nrhs = it.nrhs;
         B.tile0 = ntiles;

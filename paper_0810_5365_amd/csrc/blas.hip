@@ -388,19 +388,24 @@ wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b,
 }
 
 // ---- block Gram-Schmidt helpers (flexible GMRES) ---------------------------------------
-// <V_i, w> for i < k: w is loaded once per site, each V_i streamed past it.
+// <V_i, w> for i < k, and (with_norm) ||w||^2 as value k: one launch, one fetch.
 template <int P>
-__global__ void __launch_bounds__(RED_BLOCK) mdot_kernel(SiteRange Vs, size_t vstride, int k, SiteRange W, long long nsites,
-                                                         double* partials)
+__global__ void __launch_bounds__(RED_BLOCK) mdot_kernel(SiteRange Vs, size_t vstride, int k, int with_norm, SiteRange W,
+                                                         long long nsites, double* partials)
 {
-    for (int i = 0; i < k; ++i) {
+    const int n = k + (with_norm ? 1 : 0);
+    for (int i = 0; i < n; ++i) {
         double acc[2] = {0.0, 0.0};
         for (long long s = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; s < nsites; s += (long long)gridDim.x * RED_BLOCK) {
             const long long h = s / W.Vh;
             const uint32_t cb = (uint32_t)(s - h * W.Vh);
             typename RealOf<P>::T a[24], b[24];
-            SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.Vh, cb, a);
             SpinorIO<P>::load(W.half(h), W.Vh, cb, b);
+            if (i < k) SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.Vh, cb, a);
+            else {
+#pragma unroll
+                for (int q = 0; q < 24; ++q) a[q] = b[q];
+            }
 #pragma unroll
             for (int q = 0; q < 12; ++q) {
                 const double ar = a[2 * q], ai = a[2 * q + 1], br = b[2 * q], bi = b[2 * q + 1];
@@ -414,31 +419,34 @@ __global__ void __launch_bounds__(RED_BLOCK) mdot_kernel(SiteRange Vs, size_t vs
 }
 
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
-                    const void* w, bool fetch)
+                    const void* w, bool with_norm, bool fetch)
 {
-    if (k < 1 || 2 * k > 256) {
+    const int n = k + (with_norm ? 1 : 0);
+    if (k < 0 || n < 1 || 2 * n > 256) {
         set_error("mdot: k = %d out of range", k);
         return WD_EINVAL;
     }
-    const long long n = (long long)nh * g.Vh;
-    const int nblk = red_blocks(n);
-    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2 * k));
+    const long long ns = (long long)nh * g.Vh;
+    const int nblk = red_blocks(ns);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2 * n));
     SiteRange Vs{(const char*)V, g.Vh, half_bytes(g, prec)}, W{(const char*)w, g.Vh, half_bytes(g, prec)};
     switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(mdot_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, W, n, ctx->partials); break;
-    case WD_F32: hipLaunchKernelGGL(mdot_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, W, n, ctx->partials); break;
+    case WD_F64: hipLaunchKernelGGL(mdot_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, (int)with_norm, W, ns, ctx->partials); break;
+    case WD_F32: hipLaunchKernelGGL(mdot_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, (int)with_norm, W, ns, ctx->partials); break;
     default: set_error("mdot: precision %d not supported", prec); return WD_EUNSUPPORTED;
     }
     WD_LAUNCHED();
-    return finish(ctx, nblk, 2 * k, fetch);
+    return finish(ctx, nblk, 2 * n, fetch);
 }
 
 struct MaxpyCoef {
     float c[2 * WD_MAXPY];
 };
 
+// out = scale * (w + sum_i c_i V_i); out may be w
 template <int P>
-__global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef cf, SiteRange W, long long n)
+__global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef cf, float scale, SiteRange W, SiteRange O,
+                             long long n)
 {
     WD_SITE_LOOP(n, W.Vh)
     using T = typename RealOf<P>::T;
@@ -454,22 +462,25 @@ __global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef c
             w[2 * q + 1] += cr * v[2 * q + 1] + ci * v[2 * q];
         }
     }
-    SpinorIO<P>::store((char*)W.half(h), W.Vh, cb, w);
+#pragma unroll
+    for (int q = 0; q < 24; ++q) w[q] *= (T)scale;
+    SpinorIO<P>::store((char*)O.half(h), W.Vh, cb, w);
 }
 
 wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
-                     const double* coef, void* w)
+                     const double* coef, const void* w, double scale, void* out)
 {
-    if (k < 1 || k > WD_MAXPY) {
+    if (k < 0 || k > WD_MAXPY) {
         set_error("maxpy: k = %d out of range", k);
         return WD_EINVAL;
     }
     MaxpyCoef cf;
     for (int i = 0; i < 2 * k; ++i) cf.c[i] = (float)coef[i];
     const long long n = (long long)nh * g.Vh;
-    SiteRange Vs{(const char*)V, g.Vh, half_bytes(g, prec)}, W{(const char*)w, g.Vh, half_bytes(g, prec)};
+    SiteRange Vs{(const char*)V, g.Vh, half_bytes(g, prec)}, W{(const char*)w, g.Vh, half_bytes(g, prec)},
+        O{(const char*)out, g.Vh, half_bytes(g, prec)};
     switch (prec) {
-    case WD_F32: hipLaunchKernelGGL(maxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, Vs, vstride, k, cf, W, n); break;
+    case WD_F32: hipLaunchKernelGGL(maxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, Vs, vstride, k, cf, (float)scale, W, O, n); break;
     default: set_error("maxpy: precision %d not supported (F32 only)", prec); return WD_EUNSUPPORTED;
     }
     WD_LAUNCHED();

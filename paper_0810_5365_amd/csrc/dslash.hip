@@ -71,6 +71,7 @@ wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c
     A.par = c.par;
     A.remap = tp.remap;
     A.rhs_inner = (tp.rhs_inner && c.nrhs > 1) ? c.nrhs : 0;
+    A.gf = c.gf;
     A.zb = 0;
     if (tp.zb > 0 && tp.zb < g.L[2] && g.L[2] % tp.zb == 0) {
         A.zb = tp.zb;

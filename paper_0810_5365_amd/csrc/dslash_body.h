@@ -39,6 +39,7 @@ struct DslashArgs {
     int remap;
     int rhs_inner;   // > 1: that many rhs interleaved with the site tiles on grid x
     int zb;          // > 0: z-blocked site traversal with this block depth (divides Z)
+    int gf;          // links in temporal gauge: U_t = 1 except on the last time slice
     FastDiv dzb, dt; // division by zb and by T for the blocked traversal
 };
 
@@ -65,6 +66,16 @@ __device__ __forceinline__ uint32_t zblock_site(const DslashArgs& A, uint32_t i,
     return xh + (uint32_t)g.Xh * (y + (uint32_t)g.L[1] * (z + (uint32_t)g.L[2] * t));
 }
 
+// In temporal gauge the t-link of a hop is the identity unless the hop leaves
+// the last time slice (forward from t = T - 1, backward into t = 0), so it is
+// neither loaded nor multiplied (paper Sections 4 and 7: the gauge-fixing trick).
+template <int MU, bool FWD>
+__device__ __forceinline__ bool unit_link(const DslashArgs& A, const int c[4])
+{
+    if constexpr (MU != 3) return false;
+    else return A.gf && (FWD ? c[3] != A.g.L[3] - 1 : c[3] != 0);
+}
+
 // Loads of direction D: the link (U_mu(x) forward, U_mu(x - mu) backward)
 // and the neighbour spinor.
 template <int D, int P, int R, bool NT, typename T>
@@ -76,7 +87,7 @@ __device__ __forceinline__ void hop_load(const DslashArgs& A, uint32_t cb, const
     const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
     const int lpar = FWD ? A.par : 1 - A.par;
     const uint32_t lcb = FWD ? cb : nb;
-    LinkIO<P, R, NT>::load(A.gauge + (size_t)(2 * MU + lpar) * gbytes, A.g.Vh, lcb, u);
+    if (!unit_link<MU, FWD>(A, c)) LinkIO<P, R, NT>::load(A.gauge + (size_t)(2 * MU + lpar) * gbytes, A.g.Vh, lcb, u);
     SpinorIO<P>::load(in, A.g.Vh, nb, psi);
 }
 
@@ -96,7 +107,12 @@ __device__ __forceinline__ void hop_compute(const DslashArgs& A, const int c[4],
 #pragma unroll
     for (int k = 0; k < 12; ++k) h[k] *= sg;
     T w[12];
-    su3_mul<!FWD>(u, h, w);
+    if (unit_link<MU, FWD>(A, c)) {
+#pragma unroll
+        for (int k = 0; k < 12; ++k) w[k] = h[k];
+    } else {
+        su3_mul<!FWD>(u, h, w);
+    }
     accumulate<MU, S>(acc, w);
 }
 

@@ -114,27 +114,43 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         bool bad = false;
         for (; j < m && info->iters < prm.maxiter; ++j) {
             if (net) WD_TRY(apply_net(g, *net, Vi(j), Zi(j), fa, fb));
-            else WD_TRY(launch_convert(ctx, G, nh, WD_F32, Vi(j), WD_F32, Zi(j)));
-            WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F32, 1, Zi(j), wv));
+            WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F32, 1, net ? Zi(j) : Vi(j), wv));
             info->operator_applies++;
             info->iters++;
-            for (int pass = 0; pass < 2; ++pass) {
-                WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true));
-                std::vector<double> coef(2 * (j + 1));
+            // classical Gram-Schmidt with the norm in the same reduction; a second pass only when
+            // the projection removed most of w (Daniel-Gragg-Kaufman-Stewart criterion)
+            WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
+            double w2 = ctx->hres[2 * (j + 1)], h2 = 0.0;
+            std::vector<double> coef(2 * (j + 1));
+            for (int i = 0; i <= j; ++i) {
+                const cd h(ctx->hres[2 * i], ctx->hres[2 * i + 1]);
+                H[i][j] = h;
+                h2 += std::norm(h);
+                coef[2 * i] = -h.real();
+                coef[2 * i + 1] = -h.imag();
+            }
+            double hn2 = w2 - h2;
+            if (!(hn2 > 0.5 * w2)) {
+                WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, V, v32, j + 1, coef.data(), wv, 1.0, wv));
+                WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
+                w2 = ctx->hres[2 * (j + 1)];
+                h2 = 0.0;
                 for (int i = 0; i <= j; ++i) {
                     const cd h(ctx->hres[2 * i], ctx->hres[2 * i + 1]);
                     H[i][j] += h;
+                    h2 += std::norm(h);
                     coef[2 * i] = -h.real();
                     coef[2 * i + 1] = -h.imag();
                 }
-                WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, V, v32, j + 1, coef.data(), wv));
+                hn2 = w2 - h2;
             }
-            WD_TRY(blas_norm2(ctx, G, nh, WD_F32, wv, true));
-            const double hn = std::sqrt(ctx->hres[0]);
-            if (!std::isfinite(hn)) {
+            const double hn = std::sqrt(hn2 > 0.0 ? hn2 : 0.0);
+            if (!std::isfinite(hn) || !std::isfinite(w2)) {
                 bad = true;
                 break;
             }
+            // V_{j+1} = (w - sum h_i V_i) / hn in one pass
+            if (hn > 0.0) WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, V, v32, j + 1, coef.data(), wv, 1.0 / hn, Vi(j + 1)));
             H[j + 1][j] = hn;
             // apply the previous rotations to column j, then make a new one
             for (int i = 0; i < j; ++i) {
@@ -154,10 +170,6 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
             H[j + 1][j] = 0.0;
             gvec[j + 1] = -sn[j] * gvec[j];
             gvec[j] = std::conj(cs[j]) * gvec[j];
-            if (hn > 0.0) {
-                WD_TRY(launch_convert(ctx, G, nh, WD_F32, wv, WD_F32, Vi(j + 1)));
-                WD_TRY(blas_axpby(ctx, G, nh, WD_F32, Vi(j + 1), 1.0 / hn, WD_F32, Vi(j + 1), 0.0));
-            }
             if (std::abs(gvec[j + 1]) <= cycle_tol * beta || hn == 0.0) {
                 ++j;
                 break;
@@ -188,7 +200,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         WD_TRY(blas_zero(ctx, G, nh, WD_F32, e));
         for (int i0 = 0; i0 < j; i0 += WD_MAXPY) {
             const int k = j - i0 < WD_MAXPY ? j - i0 : WD_MAXPY;
-            WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, Zi(i0), v32, k, coef.data() + 2 * i0, e));
+            WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, net ? Zi(i0) : Vi(i0), v32, k, coef.data() + 2 * i0, e, 1.0, e));
         }
         WD_TRY(blas_axpby(ctx, G, nh, WD_F32, e, 1.0, WD_F64, x, 1.0));
         const double rr_prev = rr;

@@ -18,6 +18,8 @@
 //
 // Packed feature layout (float32): sample n, channel c, parity par, colour k,
 // site cb -> float2 at (((n C + c) 2 + par) 3 + k) Vh + cb.
+#include <stdlib.h>
+
 #include "wd_core.h"
 
 namespace wd {
@@ -331,6 +333,164 @@ __global__ void feature_pack_kernel(double* canon, float2* feat, Geom g, int C, 
     }
 }
 
+// ---- channel mixing on matrix cores ------------------------------------------------
+// For bf16 weights and C_in, C_out in {4, 8} the mixing sum_p sum_b W[p, a, b] (T_p phi^b)
+// is a real GEMM per path: rows (a, re/im) (M = 2 C_out <= 16), K = (b, re/im)
+// (2 C_in <= 16), columns (colour, site) (N = 3 x 64 per wave).  The transports run on
+// the vector units, one site per lane, and are staged through LDS as bf16 in the
+// B-operand layout; v_mfma_f32_16x16x16bf16 accumulates the nine paths in float32.
+// Operand layout of the 16x16x16 instruction: lane l holds A[l % 16][4 (l / 16) + q],
+// B[4 (l / 16) + q][l % 16] and D[4 (l / 16) + q][l % 16] for q = 0..3.
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int MF_LD = 20;   // bf16 per staged column: 16 K values + 4 of padding (40 B, conflict-free reads)
+
+template <int PATH, int R, int CIN>
+__device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
+                                         int lane, uint16_t* B)
+{
+    const int Vh = A.g.Vh;
+    float u[18];
+    uint32_t src = cb;
+    int spar = par;
+    float sign = 1.f;
+    bool dag = false;
+    if constexpr (PATH > 0) {
+        constexpr int MU = (PATH - 1) & 3;
+        constexpr bool FWD = PATH <= 4;
+        const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
+        const int lpar = FWD ? par : 1 - par;
+        LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * Vh, Vh,
+                                      FWD ? cb : nb, u);
+        sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
+        src = nb;
+        spar = 1 - par;
+        dag = !FWD;
+    }
+#pragma unroll
+    for (int b = 0; b < CIN; ++b) {
+        float v[6], t[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 q = in[fidx(b, spar, k, Vh, src)];
+            v[2 * k] = q.x;
+            v[2 * k + 1] = q.y;
+        }
+        if constexpr (PATH > 0) {
+            mat_vec(u, v, t, dag);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] *= sign;
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] = v[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = pack2<P_BF16>(t[2 * k], t[2 * k + 1]);
+    }
+}
+
+template <int PATH, int R, int CIN>
+__device__ __forceinline__ void mf_path(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4], int lane,
+                                        uint16_t* B, const bf16x4& Af, f32x4* acc)
+{
+    mf_stage<PATH, R, CIN>(A, in, par, cb, c, lane, B);
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+        const int n = t * 16 + (lane & 15);
+        const bf16x4 bf = *(const bf16x4*)&B[n * MF_LD + 4 * (lane >> 4)];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Af, bf, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+}
+
+template <int R, int CIN, int COUT>
+__global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint16_t* B = lds[wave];
+    const uint32_t Vh = (uint32_t)A.g.Vh;
+    const uint32_t site0 = (blockIdx.x * 4 + wave) * 64;
+    const uint32_t idx = site0 + lane;
+    // lanes past the end stage site 0 (in bounds); their columns are never stored
+    const uint32_t sidx = idx < 2 * Vh ? idx : 0;
+    const int par = sidx >= Vh ? 1 : 0;
+    const uint32_t cb = sidx - (uint32_t)par * Vh;
+    const float2* in = A.in + (size_t)blockIdx.y * A.in_sample;
+    float2* out = A.out + (size_t)blockIdx.y * A.out_sample;
+    int c[4];
+    cb_coords(A.g, cb, par, c);
+    // weights as A fragments, real form [[Wr, -Wi], [Wi, Wr]]
+    bf16x4 Af[9];
+    {
+        const int m = lane & 15, g = lane >> 4;
+        const int a = m >> 1, comp = m & 1;
+#pragma unroll
+        for (int p = 0; p < 9; ++p)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int k = 4 * g + q, b = k >> 1, kc = k & 1;
+                float v = 0.f;
+                if (a < COUT && b < CIN) {
+                    const float2 wv = load_w<P_BF16>(A.W, (p * COUT + a) * CIN + b);
+                    v = comp == 0 ? (kc == 0 ? wv.x : -wv.y) : (kc == 0 ? wv.y : wv.x);
+                }
+                Af[p][q] = (short)f2h<P_BF16>(v);
+            }
+    }
+    if constexpr (CIN < 8) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int h = 2 * CIN; h < 16; h += 2) *(uint32_t*)&B[(k * 64 + lane) * MF_LD + h] = 0u;
+    }
+    f32x4 acc[12];
+#pragma unroll
+    for (int t = 0; t < 12; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    mf_path<0, R, CIN>(A, in, par, cb, c, lane, B, Af[0], acc);
+    mf_path<1, R, CIN>(A, in, par, cb, c, lane, B, Af[1], acc);
+    mf_path<2, R, CIN>(A, in, par, cb, c, lane, B, Af[2], acc);
+    mf_path<3, R, CIN>(A, in, par, cb, c, lane, B, Af[3], acc);
+    mf_path<4, R, CIN>(A, in, par, cb, c, lane, B, Af[4], acc);
+    mf_path<5, R, CIN>(A, in, par, cb, c, lane, B, Af[5], acc);
+    mf_path<6, R, CIN>(A, in, par, cb, c, lane, B, Af[6], acc);
+    mf_path<7, R, CIN>(A, in, par, cb, c, lane, B, Af[7], acc);
+    mf_path<8, R, CIN>(A, in, par, cb, c, lane, B, Af[8], acc);
+    const int g = lane >> 4;
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+        const int n = t * 16 + (lane & 15);
+        const int k = n >> 6;
+        const uint32_t s = site0 + (n & 63);
+        if (s >= 2 * Vh) continue;
+        const int sp = s >= Vh ? 1 : 0;
+        const uint32_t scb = s - (uint32_t)sp * Vh;
+        if (2 * g < COUT) out[fidx(2 * g, sp, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
+        if (2 * g + 1 < COUT) out[fidx(2 * g + 1, sp, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
+    }
+}
+
+template <int R>
+static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples)
+{
+    dim3 grid((2 * A.g.Vh + 255) / 256, nsamples), block(256);
+    if (cin == 4 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8>), grid, block, 0, ctx->stream, A);
+    else if (cin == 8 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8>), grid, block, 0, ctx->stream, A);
+    else if (cin == 8 && cout == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4>), grid, block, 0, ctx->stream, A);
+    else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4>), grid, block, 0, ctx->stream, A);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+static bool use_mfma(int wprec, int cin, int cout)
+{
+    if (wprec != WD_BF16 || (cin != 4 && cin != 8) || (cout != 4 && cout != 8)) return false;
+    const char* e = getenv("WD_PTCONV_MFMA");
+    return !(e && atoi(e) == 0);
+}
+
 // ---- launchers ---------------------------------------------------------------------------
 template <int R, int WP>
 static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples)
@@ -361,6 +521,7 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
     A.in_sample = (long long)cin * 6 * g->geom.Vh;
     A.out_sample = (long long)cout * 6 * g->geom.Vh;
     const bool r12 = g->recon == 12;
+    if (use_mfma(wprec, cin, cout)) return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples) : mfma_r<18>(g->ctx, A, cin, cout, nsamples);
     switch (wprec) {
     case WD_F32: return r12 ? fwd_r_w<12, P_F32>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F32>(g->ctx, A, cout, nsamples);
     case WD_F16: return r12 ? fwd_r_w<12, P_F16>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F16>(g->ctx, A, cout, nsamples);

@@ -113,6 +113,7 @@ wd_status autotune_dslash(wd_gauge g, int prec, int nrhs, int* ntuned)
             c.dagger = dagger;
             c.prec = prec;
             c.recon = g->recon;
+            c.gf = g->gf ? 1 : 0;
             TuneParam best;
             float best_us = 1e30f;
             std::vector<int> zbs{0};

@@ -85,6 +85,7 @@ struct wd_gauge_s {
     double* canon = nullptr;       // float64 canonical links on the device
     void* packed[4] = {nullptr, nullptr, nullptr, nullptr};   // per wd_prec
     bool uploaded = false;
+    bool gf = false;               // temporal gauge fixed by wd_gauge_fix_temporal
 };
 
 namespace wd {
@@ -107,6 +108,7 @@ struct DslashCall {
     int dagger = 0;
     int prec = WD_F32;
     int recon = 12;
+    int gf = 0;                    // links in temporal gauge (unit t-links but the last slice)
 };
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
@@ -134,13 +136,14 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
-// h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[2i], dres[2i + 1]
+// h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[2i], dres[2i + 1];
+// with_norm adds ||w||^2 in dres[2k]
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
-                    const void* w, bool fetch);
-// w += sum_i c_i V_i, complex c_i = (coef[2i], coef[2i + 1]), i < k <= WD_MAXPY
+                    const void* w, bool with_norm, bool fetch);
+// out = scale (w + sum_i c_i V_i), complex c_i = (coef[2i], coef[2i + 1]), i < k <= WD_MAXPY; out may be w
 constexpr int WD_MAXPY = 64;
 wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
-                     const double* coef, void* w);
+                     const double* coef, const void* w, double scale, void* out);
 
 // ---- ptconv.hip ----------------------------------------------------------------
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples);

@@ -71,6 +71,7 @@ _PROTOS = {
     "wd_gauge_prepare": ("status", [_V, _I]),
     "wd_gauge_bytes": (_S, [_V, _I]),
     "wd_gauge_destroy": ("status", [_V]),
+    "wd_gauge_fix_temporal": ("status", [_V, _V]),
     "wd_spinor_bytes": (_S, [_P(WdLattice), _I, _I, _I]),
     "wd_spinor_pack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),
     "wd_spinor_unpack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),

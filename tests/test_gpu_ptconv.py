@@ -51,8 +51,10 @@ def test_forward_matches_oracle(env, cin, cout):
 
 
 @pytest.mark.parametrize("wprec", ["bf16", "f16"])
-def test_forward_16bit_weights(env, wprec):
+def test_forward_16bit_weights(env, wprec, monkeypatch):
+    """Vector-unit path with 16-bit weights: exact up to float32 against the oracle with the same weights."""
     import torch
+    monkeypatch.setenv("WD_PTCONV_MFMA", "0")
     w, ctx, U, g, lat = env
     cin, cout = 4, 8
     phi = feat(cin, 31)
@@ -169,3 +171,26 @@ def test_forward_gauge_covariance_on_gpu(env):
         res.append(w.unpack_features(ctx, lat, out, (cout,) + phi.shape[1:], cout))
     assert orc.rel_l2(res[1], rot(res[0])) < 1e-5
     gO.close()
+
+
+@pytest.mark.parametrize("cin,cout", [(4, 8), (8, 8), (8, 4), (4, 4)])
+def test_forward_matrix_core_path(env, cin, cout, monkeypatch):
+    """bf16 weights on the MFMA path: the transported inputs are rounded to bf16
+    (relative 2^-9 each), so the layer output is within ~2e-3 of the oracle with the
+    same weights; bound 1e-2.  Two samples, ragged site count per workgroup."""
+    import torch
+    monkeypatch.setenv("WD_PTCONV_MFMA", "1")
+    w, ctx, U, g, lat = env
+    n = 2
+    phi = feat(cin, 100 + cin, n)
+    W = ls.gaussian_complex((9, cout, cin), 101 + cout)
+    Wq = as_torch_weights(W).to(torch.bfloat16).contiguous()
+    Wref = orc.round16(W.real.astype(np.float32), "bf16") + 1j * orc.round16(W.imag.astype(np.float32), "bf16")
+    fin = w.pack_features(ctx, lat, phi, cin, n)
+    out = w.pack_features(ctx, lat, np.zeros((n, cout) + phi.shape[2:], complex), cout, n)
+    w.wd_ptconv_forward(g.handle, cin, cout, w.BF16, n, Wq.data_ptr(), fin.data_ptr(), out.data_ptr())
+    got = w.unpack_features(ctx, lat, out, (n, cout) + phi.shape[2:], cout, n)
+    for s in range(n):
+        err = orc.rel_l2(got[s], orc.ptconv_forward(U, phi[s], Wref.astype(np.complex128), BC))
+        assert err < 1e-2, err
+        assert err > 1e-6          # it did run in bf16
