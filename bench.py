@@ -185,6 +185,31 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
     return out
 
 
+def learned_extras(w, ctx):
+    """Time to an FP64-verified 1e-10 Wilson-system residual on 16^3 x 32 (eps 0.7, kappa 0.1248),
+    four gauge fields unseen in training: plain FP32 CG (with FP64 reliable updates), flexible
+    GMRES without and with the committed trained network (bf16 weights on the matrix cores)."""
+    import numpy as np
+    from paper_0810_5365_amd import learn
+    net = learn.load_net(learn.DEFAULT_WEIGHTS, w.BF16)
+    dims, kappa = (16, 16, 16, 32), 0.1248
+    rows = []
+    for seed in (6001, 6002, 6003, 6004):
+        f = learn.Field(ctx, dims, 0.7, seed)
+        learn.solve_compare(net, f, kappa)          # first call: packing, tuning-free warm-up
+        r = learn.solve_compare(net, f, kappa)
+        rows.append({k: {kk: v[kk] for kk in ("iters", "wall_s", "true_resid_M", "fell_back")}
+                     for k, v in r.items() if isinstance(v, dict)})
+        f.close()
+    out = {"lattice": list(dims), "eps": 0.7, "kappa": kappa, "tol": 1e-10, "fields": [6001, 6002, 6003, 6004],
+           "weights": "paper_0810_5365_amd/data/" + __import__("os").path.basename(learn.DEFAULT_WEIGHTS), "per_field": rows}
+    for k in rows[0]:
+        out["mean_" + k] = {"iters": float(np.mean([r[k]["iters"] for r in rows])),
+                            "wall_ms": round(1e3 * float(np.mean([r[k]["wall_s"] for r in rows])), 3)}
+    out["learned_speedup_vs_plain_cg"] = round(out["mean_plain_cg_f32"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -338,6 +363,8 @@ def main():
         rec["extras"] = extras(w, ctx, stream, torch, ls)
         print("bench: 32^3x64 solves", file=sys.stderr, flush=True)
         rec["solve_32c64"] = solve_extras(w, ctx, torch, ls)
+        print("bench: learned vs plain solves on 16^3x32", file=sys.stderr, flush=True)
+        rec["solve_learned_16c32"] = learned_extras(w, ctx)
     if not args.no_cpu:
         print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(U, psi_e, dims)

@@ -251,6 +251,15 @@ wd_status wd_batch_destroy(wd_batch b);
  * with, and the reference for hardware byte counters.  Asynchronous. */
 wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t bytes);
 
+/* Solve M x = b on the full lattice through the even-odd Schur complement with
+ * BiCGstab on Mhat x_e = b_e + kappa D_eo b_o (paper, Section 7: the second
+ * inverter).  params->sloppy must be F32 or F64; reliable updates recompute
+ * bhat - Mhat x in float64 when the iterated residual drops below delta times
+ * its running maximum.  true_resid is ||bhat - Mhat x_e|| / ||b||,
+ * true_resid_M the full-system ||b - M x|| / ||b||.  Synchronous. */
+wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
+                            wd_solver_info* info);
+
 /* ---- learned-preconditioner solve ---------------------------------------------- */
 /* Solve M x = b on the full lattice (b, x: FULL float64 packed fields; x is the
  * initial guess) by flexible GMRES with right preconditioner N, a stack of

@@ -1,0 +1,179 @@
+// BiCGstab (van der Vorst 1992) on the even-odd Schur system Mhat x_e = bhat_e
+// (the paper's second inverter, Section 7), with the same mixed-precision
+// scheme as the CG: iterations in float32 or float64 storage and arithmetic,
+// solution accumulated in float64 through reliable updates that recompute
+// r = bhat - Mhat x in float64; the final residual is that of the full system.
+#include <chrono>
+#include <cmath>
+#include <complex>
+
+#include "wd_ops.h"
+
+namespace wd {
+
+typedef std::complex<double> cd;
+
+static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& prm, const void* bhat, double bnorm2,
+                              void* x, wd_solver_info* info)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    const int ps = prm.sloppy == WD_F64 ? WD_F64 : WD_F32;
+    const size_t hs = half_bytes(G, ps), h64 = half_bytes(G, WD_F64);
+    void *r, *t64, *rs, *r0, *p, *v, *s, *t, *xs;
+    WD_TRY(ws_get(ctx, "bicg.r", h64, &r));
+    WD_TRY(ws_get(ctx, "bicg.t64", h64, &t64));
+    WD_TRY(ws_get(ctx, "bicg.rs", hs, &rs));
+    WD_TRY(ws_get(ctx, "bicg.r0", hs, &r0));
+    WD_TRY(ws_get(ctx, "bicg.p", hs, &p));
+    WD_TRY(ws_get(ctx, "bicg.v", hs, &v));
+    WD_TRY(ws_get(ctx, "bicg.s", hs, &s));
+    WD_TRY(ws_get(ctx, "bicg.t", hs, &t));
+    WD_TRY(ws_get(ctx, "bicg.xs", hs, &xs));
+    const double target = prm.tol * prm.tol * bnorm2;
+    auto true_res = [&](double* rr) -> wd_status {
+        WD_TRY(op_M(g, kappa, WD_EVEN, 0, WD_F64, 1, x, t64));
+        WD_TRY(blas_xmy_norm(ctx, G, 1, bhat, t64, r, true));
+        *rr = ctx->hres[0];
+        info->operator_applies++;
+        return WD_OK;
+    };
+    auto dot = [&](const void* a, const void* b, cd* out) -> wd_status {
+        WD_TRY(blas_dot(ctx, G, 1, ps, a, b, true));
+        *out = cd(ctx->hres[0], ctx->hres[1]);
+        return WD_OK;
+    };
+    double rr;
+    WD_TRY(true_res(&rr));
+    WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, rs));
+    WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, r0));
+    WD_TRY(blas_zero(ctx, G, 1, ps, p));
+    WD_TRY(blas_zero(ctx, G, 1, ps, v));
+    WD_TRY(blas_zero(ctx, G, 1, ps, xs));
+    cd rho(1.0), alpha(1.0), omega(1.0);
+    double maxrr = rr;
+    bool dirty = false;
+    wd_status status = WD_ENOCONV;
+    if (rr <= target) status = WD_OK;
+    while (status != WD_OK && info->iters < prm.maxiter) {
+        cd rho_new;
+        WD_TRY(dot(r0, rs, &rho_new));
+        if (!std::isfinite(rho_new.real()) || std::abs(rho_new) == 0.0) {
+            set_error("BiCGstab breakdown: rho = 0 at iteration %d", info->iters);
+            status = WD_ENAN;
+            break;
+        }
+        const cd beta = (rho_new / rho) * (alpha / omega);
+        // p = r + beta (p - omega v)
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, -omega.real(), -omega.imag(), v, 1.0, 0.0, p));
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, 1.0, 0.0, rs, beta.real(), beta.imag(), p));
+        WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, p, v));
+        cd r0v;
+        WD_TRY(dot(r0, v, &r0v));
+        alpha = rho_new / r0v;
+        // s = r - alpha v
+        WD_TRY(launch_convert(ctx, G, 1, ps, rs, ps, s));
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, -alpha.real(), -alpha.imag(), v, 1.0, 0.0, s));
+        WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, s, t));
+        info->operator_applies += 2;
+        cd ts;
+        WD_TRY(dot(t, s, &ts));
+        WD_TRY(blas_norm2(ctx, G, 1, ps, t, true));
+        const double tt = ctx->hres[0];
+        omega = tt > 0.0 ? ts / tt : cd(0.0);
+        // x_s += alpha p + omega s ; r = s - omega t
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, alpha.real(), alpha.imag(), p, 1.0, 0.0, xs));
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, omega.real(), omega.imag(), s, 1.0, 0.0, xs));
+        WD_TRY(blas_cxpby(ctx, G, 1, ps, -omega.real(), -omega.imag(), t, 1.0, 0.0, s));
+        std::swap(rs, s);
+        dirty = true;
+        rho = rho_new;
+        info->iters++;
+        WD_TRY(blas_norm2(ctx, G, 1, ps, rs, true));
+        double rr_s = ctx->hres[0];
+        if (!std::isfinite(rr_s) || std::abs(omega) == 0.0) {
+            set_error("BiCGstab breakdown at iteration %d", info->iters);
+            status = WD_ENAN;
+            break;
+        }
+        if (rr_s <= target || rr_s < prm.delta * prm.delta * maxrr) {
+            WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
+            WD_TRY(blas_zero(ctx, G, 1, ps, xs));
+            dirty = false;
+            WD_TRY(true_res(&rr));
+            info->reliable_updates++;
+            if (rr <= target) {
+                status = WD_OK;
+                break;
+            }
+            WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, rs));
+            maxrr = rr;
+        } else if (rr_s > maxrr) {
+            maxrr = rr_s;
+        }
+    }
+    if (dirty) WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
+    WD_TRY(true_res(&rr));
+    info->true_resid = std::sqrt(rr / bnorm2);
+    if (status != WD_ENAN) status = rr <= target ? WD_OK : WD_ENOCONV;
+    return status;
+}
+
+} // namespace wd
+
+using namespace wd;
+
+extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
+                                       wd_solver_info* info)
+{
+    if (!g || !params || !b || !x || !info) {
+        set_error("wd_bicgstab_solve: NULL argument");
+        return WD_EINVAL;
+    }
+    if (!(params->tol > 0.0) || params->maxiter < 0 || !valid_prec(params->sloppy) || params->delta < 0.0 ||
+        params->delta >= 1.0) {
+        set_error("wd_bicgstab_solve: bad solver params");
+        return WD_EINVAL;
+    }
+    if (params->sloppy == WD_F16 || params->sloppy == WD_BF16) {
+        set_error("wd_bicgstab_solve: sloppy precision must be F32 or F64");
+        return WD_EUNSUPPORTED;
+    }
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    WD_HIP(hipStreamSynchronize(ctx->stream));
+    const auto t0 = std::chrono::steady_clock::now();
+    *info = wd_solver_info{};
+    const long long hb = (long long)half_bytes(G, WD_F64);
+    const char* b_e = (const char*)b;
+    const char* b_o = b_e + hb;
+    char* x_e = (char*)x;
+    char* x_o = x_e + hb;
+    void* bhat;
+    WD_TRY(ws_get(ctx, "bicg.bhat", hb, &bhat));
+    WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, hb, bhat, hb, b_e, hb, 1.0, kappa));
+    WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
+    const double bb = ctx->hres[0];
+    wd_status s = WD_OK;
+    if (bb > 0.0) {
+        s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info);
+        if (s != WD_OK && s != WD_ENOCONV) return s;
+    } else {
+        WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
+    }
+    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
+    void *t, *r;
+    WD_TRY(ws_get(ctx, "wilson.t", 2 * hb, &t));
+    WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
+    WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
+    WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
+    info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
+    info->operator_applies++;
+    info->status = s;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return s;
+}

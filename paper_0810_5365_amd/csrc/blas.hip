@@ -387,6 +387,39 @@ wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b,
     return finish(ctx, nblk, 1, fetch);
 }
 
+// ---- y = a x + b y with complex a, b --------------------------------------------------------
+template <int P>
+__global__ void cxpby_kernel(SiteRange X, SiteRange Y, long long n, double ar, double ai, double br, double bi)
+{
+    WD_SITE_LOOP(n, X.Vh)
+    using T = typename RealOf<P>::T;
+    T x[24], y[24];
+    SpinorIO<P>::load(X.half(h), X.Vh, cb, x);
+    SpinorIO<P>::load(Y.half(h), Y.Vh, cb, y);
+    const T a0 = (T)ar, a1 = (T)ai, b0 = (T)br, b1 = (T)bi;
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        const T xr = x[2 * q], xi = x[2 * q + 1], yr = y[2 * q], yi = y[2 * q + 1];
+        y[2 * q] = a0 * xr - a1 * xi + b0 * yr - b1 * yi;
+        y[2 * q + 1] = a0 * xi + a1 * xr + b0 * yi + b1 * yr;
+    }
+    SpinorIO<P>::store((char*)Y.half(h), Y.Vh, cb, y);
+}
+
+wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nh, int prec, double ar, double ai, const void* x, double br,
+                     double bi, void* y)
+{
+    const long long n = (long long)nh * g.Vh;
+    SiteRange X{(const char*)x, g.Vh, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, half_bytes(g, prec)};
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL(cxpby_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
+    case WD_F32: hipLaunchKernelGGL(cxpby_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
+    default: set_error("cxpby: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
 // ---- block Gram-Schmidt helpers (flexible GMRES) ---------------------------------------
 // <V_i, w> for i < k, and (with_norm) ||w||^2 as value k: one launch, one fetch.
 template <int P>

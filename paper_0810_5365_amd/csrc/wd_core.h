@@ -125,6 +125,9 @@ wd_status launch_convert(wd_context ctx, const Geom& g, size_t nhalves, int sp, 
 wd_status blas_dot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, const void* b, bool fetch);
 wd_status blas_norm2(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, bool fetch);
 wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, double ar, double ai, const void* x, void* y);
+// y = a x + b y, complex a = (ar, ai), b = (br, bi); F32 and F64
+wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nhalves, int prec, double ar, double ai, const void* x, double br,
+                     double bi, void* y);
 wd_status blas_zero(wd_context ctx, const Geom& g, size_t nhalves, int prec, void* x);
 // y = a*x + b*y with real a, b (y, x may differ in precision: x at px, y at py)
 wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nhalves, int px, const void* x, double a, int py, void* y, double b);

@@ -190,6 +190,21 @@ def solve_compare(net, field, kappa, tol=1e-10, restart=16, seed=4242, maxiter=4
     return res
 
 
+def load_net(path, wprec=w.BF16, device="cuda"):
+    """A PTNet with the float32 weights saved by `main(--save ...)`."""
+    d = np.load(path)
+    widths = tuple(int(c) for c in d["widths"])
+    net = pt.PTNet(widths, wprec, device=device)
+    with torch.no_grad():
+        for k, Wp in enumerate(net.weights):
+            Wp.copy_(torch.from_numpy(d["arr_%d" % k]))
+    return net
+
+
+DEFAULT_WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(__file__), "data",
+                                             "ptnet_16c32_eps0.7_kappa0.1248.npz")
+
+
 def main(argv=None):
     """Train on seeded fields and compare solvers on unseen ones; prints one JSON line.
 

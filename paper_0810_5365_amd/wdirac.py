@@ -97,6 +97,7 @@ _PROTOS = {
     "wd_batch_info": ("status", [_V, _P(ctypes.c_longlong), _P(_I)]),
     "wd_batch_destroy": ("status", [_V]),
     "wd_device_copy": ("status", [_V, _V, _V, _S]),
+    "wd_bicgstab_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
     "wd_fgmres_solve": ("status", [_V, _D, _P(WdSolverParams), _I, _I, _P(_I), _P(_V), _I, _V, _V, _P(WdSolverInfo)]),
     "wd_autotune_dslash": ("status", [_V, _I, _I, ctypes.c_char_p]),
     "wd_tune_save": ("status", [_V, ctypes.c_char_p]),
