@@ -250,12 +250,13 @@ wd_status wd_context_create(int device, void* stream, wd_context* out)
     c->device = device;
     c->stream = (hipStream_t)stream;
     if (hipMalloc(&c->dres, 256 * sizeof(double)) != hipSuccess ||
-        hipHostMalloc(&c->hres, 256 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc(&c->hres, 256 * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
         set_error("wd_context_create: allocation failed");
         if (c->dres) hipFree(c->dres);
         delete c;
         return WD_ENOMEM;
     }
+    if (hipHostGetDevicePointer((void**)&c->hres_dev, c->hres, 0) != hipSuccess) c->hres_dev = nullptr;
     wd_status s = ensure_reduction(c, 4 * 2048);
     if (s != WD_OK) {
         hipFree(c->dres);

@@ -51,22 +51,23 @@ template <int N> __device__ __forceinline__ void block_reduce(double* v, double*
     }
 }
 
-__global__ void __launch_bounds__(RED_BLOCK) finish_kernel(const double* __restrict__ partials, int nblk, int n,
-                                                           double* __restrict__ out)
+// One workgroup per reduced value: partials of value k summed in a fixed order, the
+// result written to device memory and to the mapped pinned host copy.
+__global__ void __launch_bounds__(RED_BLOCK) finish_kernel(const double* __restrict__ partials, int nblk,
+                                                           double* __restrict__ out, double* __restrict__ host_out)
 {
     __shared__ double lds[RED_BLOCK / 64];
-    for (int k = 0; k < n; ++k) {
-        double s = 0.0;
-        for (int i = threadIdx.x; i < nblk; i += RED_BLOCK) s += partials[(size_t)k * nblk + i];
-        s = wave_sum(s);
-        if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int w = 0; w < RED_BLOCK / 64; ++w) t += lds[w];
-            out[k] = t;
-        }
-        __syncthreads();
+    const int k = blockIdx.x;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RED_BLOCK) s += partials[(size_t)k * nblk + i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RED_BLOCK / 64; ++w) t += lds[w];
+        out[k] = t;
+        if (host_out) host_out[k] = t;
     }
 }
 
@@ -78,7 +79,8 @@ static int red_blocks(long long nsites)
 
 static wd_status finish(wd_context ctx, int nblk, int n, bool fetch)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, n, ctx->dres);
+    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, ctx->dres,
+                       ctx->hres_dev);
     WD_LAUNCHED();
     if (fetch) return fetch_results(ctx, n);
     return WD_OK;
@@ -86,7 +88,8 @@ static wd_status finish(wd_context ctx, int nblk, int n, bool fetch)
 
 wd_status fetch_results(wd_context ctx, int n)
 {
-    WD_HIP(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    if (!ctx->hres_dev)   // no mapped host buffer: copy the results over
+        WD_HIP(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
     WD_HIP(hipStreamSynchronize(ctx->stream));
     return WD_OK;
 }

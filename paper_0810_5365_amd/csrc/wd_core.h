@@ -43,10 +43,10 @@ void clear_error();
 // Launch shape of one kernel: workgroup size, XCD-aware block remap, and
 // non-temporal (streaming) link loads.
 struct TuneParam {
-    int block = 256;
+    int block = 64;
     int remap = 1;
-    int nt = 0;   // non-temporal link loads
-    int pf = 0;   // software-pipelined directions
+    int nt = 1;   // non-temporal link loads
+    int pf = 1;   // software-pipelined directions
     int rhs_inner = 1;   // several rhs: interleave them with the site tiles
     int zb = 0;          // z-blocked site traversal depth (0: natural order)
 };
@@ -72,7 +72,8 @@ struct wd_context_s {
     double* partials = nullptr;
     size_t npartials = 0;
     double* dres = nullptr;    // device results
-    double* hres = nullptr;    // pinned host copy
+    double* hres = nullptr;    // pinned host copy (mapped: kernels write it directly)
+    double* hres_dev = nullptr;   // device address of hres, or null if it is not mapped
     std::map<std::string, wd::TuneParam> tune;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
