@@ -39,7 +39,12 @@
  *   spinor FULL      [nrhs][T][Z][Y][X][4][3][2]   [spin][colour]
  *   spinor EVEN/ODD  [nrhs][V/2][4][3][2]          sites of that parity in cb order
  * Packed (device) layouts are internal; wd_spinor_bytes gives their size.  A
- * packed FULL field is the EVEN half followed by the ODD half, per rhs.
+ * packed FULL field is the EVEN half followed by the ODD half, per rhs.  Inside
+ * a half field (and a packed gauge group) the structure-of-arrays planes lie
+ * wd_plane_stride() sites apart: V/2 below 4096 sites per parity, otherwise
+ * V/2 rounded up to 64 plus 256, so that planes never sit a power of two bytes
+ * apart and the streams of one kernel spread over the HBM channels.  The tail
+ * of each plane is padding that no function reads.
  */
 #ifndef WDIRAC_H
 #define WDIRAC_H
@@ -123,6 +128,9 @@ wd_status wd_gauge_fix_temporal(wd_gauge g, double* omega_out);
  *      stored as structure-of-arrays of 16-byte vectors) ---------------------- */
 /* Bytes of a packed field; 0 on bad input. */
 size_t wd_spinor_bytes(const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs);
+/* Sites between consecutive planes of a packed half field (see the layout
+ * notes above); 0 on bad input. */
+long long wd_plane_stride(const wd_lattice* lat);
 /* canonical float64 (device) -> packed (device), and back.  16-bit precisions
  * quantise each site with scale s = max |v_i| over its 24 float32 values and
  * codes RNE16(v_i * RN(1/s)). */

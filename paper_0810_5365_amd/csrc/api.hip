@@ -44,7 +44,7 @@ wd_status make_geom(const wd_lattice* lat, Geom* g)
             return WD_EINVAL;
         }
         V *= L;
-        if (V / 2 >= (1ll << 31)) {
+        if (plane_stride(V / 2) >= (1ll << 31)) {
             set_error("half volume exceeds 2^31 - 1");
             return WD_ESHAPE;
         }
@@ -57,6 +57,7 @@ wd_status make_geom(const wd_lattice* lat, Geom* g)
     }
     g->Xh = g->L[0] / 2;
     g->Vh = (int)(V / 2);
+    g->ps = (int)plane_stride(V / 2);
     g->st[0] = 1;
     g->st[1] = g->Xh;
     g->st[2] = g->Xh * g->L[1];
@@ -121,7 +122,7 @@ wd_status gauge_links(wd_gauge g, int prec, const void** out)
     }
     if (!g->packed[prec]) {
         void* p = nullptr;
-        const size_t bytes = 8 * link_site_bytes(prec, g->recon) * (size_t)g->geom.Vh;
+        const size_t bytes = 8 * link_site_bytes(prec, g->recon) * (size_t)g->geom.ps;
         WD_HIP(hipSetDevice(g->ctx->device));
         WD_HIP(hipMalloc(&p, bytes));
         wd_status s = launch_pack_gauge(g->ctx, g->geom, prec, g->recon, g->canon, p);
@@ -354,7 +355,7 @@ wd_status wd_gauge_prepare(wd_gauge g, wd_prec prec)
 size_t wd_gauge_bytes(wd_gauge g, wd_prec prec)
 {
     if (!g || !valid_prec(prec)) return 0;
-    return 8 * link_site_bytes(prec, g->recon) * (size_t)g->geom.Vh;
+    return 8 * link_site_bytes(prec, g->recon) * (size_t)g->geom.ps;
 }
 
 wd_status wd_gauge_destroy(wd_gauge g)
@@ -378,6 +379,13 @@ size_t wd_spinor_bytes(const wd_lattice* lat, wd_subset subset, wd_prec prec, in
     if (!valid_prec(prec) || !valid_subset(subset) || nrhs < 1) return 0;
     if (make_geom(lat, &g) != WD_OK) return 0;
     return half_bytes(g, prec) * halves_of(subset, nrhs);
+}
+
+long long wd_plane_stride(const wd_lattice* lat)
+{
+    Geom g;
+    if (make_geom(lat, &g) != WD_OK) return 0;
+    return g.ps;
 }
 
 static wd_status field_args(const wd_lattice* lat, int subset, int prec, int nrhs, Geom* g)

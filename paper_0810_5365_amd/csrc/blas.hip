@@ -18,7 +18,8 @@ constexpr int RED_MAXBLOCKS = 2048;
 
 struct SiteRange {
     const char* base;
-    int Vh;
+    int Vh;      // sites per half field
+    int ps;      // plane stride of a half field
     size_t hb;   // bytes of one half field
     __device__ __forceinline__ const char* half(long long h) const { return base + (size_t)h * hb; }
 };
@@ -103,10 +104,10 @@ __global__ void __launch_bounds__(RED_BLOCK) dot_kernel(SiteRange A, SiteRange B
         const long long h = k / A.Vh;
         const uint32_t cb = (uint32_t)(k - h * A.Vh);
         typename RealOf<P>::T a[24];
-        SpinorIO<P>::load(A.half(h), A.Vh, cb, a);
+        SpinorIO<P>::load(A.half(h), A.ps, cb, a);
         if constexpr (DOT) {
             typename RealOf<P>::T b[24];
-            SpinorIO<P>::load(B.half(h), B.Vh, cb, b);
+            SpinorIO<P>::load(B.half(h), B.ps, cb, b);
 #pragma unroll
             for (int i = 0; i < 12; ++i) {
                 const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
@@ -127,7 +128,7 @@ static wd_status dot_t(wd_context ctx, const Geom& g, size_t nh, const void* a, 
     const long long n = (long long)nh * g.Vh;
     const int nblk = red_blocks(n);
     WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2));
-    SiteRange A{(const char*)a, g.Vh, half_bytes(g, P)}, B{(const char*)b, g.Vh, half_bytes(g, P)};
+    SiteRange A{(const char*)a, g.Vh, g.ps, half_bytes(g, P)}, B{(const char*)b, g.Vh, g.ps, half_bytes(g, P)};
     hipLaunchKernelGGL((dot_kernel<P, DOT>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials);
     WD_LAUNCHED();
     return finish(ctx, nblk, DOT ? 2 : 1, fetch);
@@ -172,8 +173,8 @@ __global__ void caxpy_kernel(SiteRange X, SiteRange Y, long long n, double ar, d
     WD_SITE_LOOP(n, X.Vh)
     using T = typename RealOf<P>::T;
     T x[24], y[24];
-    SpinorIO<P>::load(X.half(h), X.Vh, cb, x);
-    SpinorIO<P>::load(Y.half(h), Y.Vh, cb, y);
+    SpinorIO<P>::load(X.half(h), X.ps, cb, x);
+    SpinorIO<P>::load(Y.half(h), Y.ps, cb, y);
     const T a = (T)ar, b = (T)ai;
 #pragma unroll
     for (int i = 0; i < 12; ++i) {
@@ -181,13 +182,13 @@ __global__ void caxpy_kernel(SiteRange X, SiteRange Y, long long n, double ar, d
         y[2 * i] += a * xr - b * xi;
         y[2 * i + 1] += a * xi + b * xr;
     }
-    SpinorIO<P>::store((char*)Y.half(h), Y.Vh, cb, y);
+    SpinorIO<P>::store((char*)Y.half(h), Y.ps, cb, y);
 }
 
 wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nh, int prec, double ar, double ai, const void* x, void* y)
 {
     const long long n = (long long)nh * g.Vh;
-    SiteRange X{(const char*)x, g.Vh, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, half_bytes(g, prec)};
+    SiteRange X{(const char*)x, g.Vh, g.ps, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
     case WD_F64: hipLaunchKernelGGL(caxpy_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai); break;
     case WD_F32: hipLaunchKernelGGL(caxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai); break;
@@ -198,13 +199,13 @@ wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nh, int prec, double 
 }
 
 template <int P>
-__global__ void zero_kernel(char* base, int Vh, size_t hb, long long n)
+__global__ void zero_kernel(char* base, int Vh, int ps, size_t hb, long long n)
 {
     WD_SITE_LOOP(n, Vh)
     typename RealOf<P>::T z[24];
 #pragma unroll
     for (int i = 0; i < 24; ++i) z[i] = 0;
-    SpinorIO<P>::store(base + (size_t)h * hb, Vh, cb, z);
+    SpinorIO<P>::store(base + (size_t)h * hb, ps, cb, z);
 }
 
 wd_status blas_zero(wd_context ctx, const Geom& g, size_t nh, int prec, void* x)
@@ -212,10 +213,10 @@ wd_status blas_zero(wd_context ctx, const Geom& g, size_t nh, int prec, void* x)
     const long long n = (long long)nh * g.Vh;
     const size_t hb = half_bytes(g, prec);
     switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(zero_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
-    case WD_F32: hipLaunchKernelGGL(zero_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
-    case WD_F16: hipLaunchKernelGGL(zero_kernel<P_F16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
-    case WD_BF16: hipLaunchKernelGGL(zero_kernel<P_BF16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, hb, n); break;
+    case WD_F64: hipLaunchKernelGGL(zero_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, g.ps, hb, n); break;
+    case WD_F32: hipLaunchKernelGGL(zero_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, g.ps, hb, n); break;
+    case WD_F16: hipLaunchKernelGGL(zero_kernel<P_F16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, g.ps, hb, n); break;
+    case WD_BF16: hipLaunchKernelGGL(zero_kernel<P_BF16>, site_grid(n), dim3(256), 0, ctx->stream, (char*)x, g.Vh, g.ps, hb, n); break;
     default: set_error("zero: bad precision %d", prec); return WD_EINVAL;
     }
     WD_LAUNCHED();
@@ -230,11 +231,11 @@ __global__ void axpby_kernel(SiteRange X, SiteRange Y, long long n, double a, do
     using T = typename std::conditional<(PX == P_F64 || PY == P_F64), double, float>::type;
     typename RealOf<PX>::T x[24];
     typename RealOf<PY>::T y[24];
-    SpinorIO<PX>::load(X.half(h), X.Vh, cb, x);
-    SpinorIO<PY>::load(Y.half(h), Y.Vh, cb, y);
+    SpinorIO<PX>::load(X.half(h), X.ps, cb, x);
+    SpinorIO<PY>::load(Y.half(h), Y.ps, cb, y);
 #pragma unroll
     for (int i = 0; i < 24; ++i) y[i] = (typename RealOf<PY>::T)((T)a * (T)x[i] + (T)b * (T)y[i]);
-    SpinorIO<PY>::store((char*)Y.half(h), Y.Vh, cb, y);
+    SpinorIO<PY>::store((char*)Y.half(h), Y.ps, cb, y);
 }
 
 template <int PX>
@@ -254,7 +255,7 @@ static wd_status axpby_x(wd_context ctx, long long n, SiteRange X, SiteRange Y, 
 wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nh, int px, const void* x, double a, int py, void* y, double b)
 {
     const long long n = (long long)nh * g.Vh;
-    SiteRange X{(const char*)x, g.Vh, half_bytes(g, px)}, Y{(const char*)y, g.Vh, half_bytes(g, py)};
+    SiteRange X{(const char*)x, g.Vh, g.ps, half_bytes(g, px)}, Y{(const char*)y, g.Vh, g.ps, half_bytes(g, py)};
     switch (px) {
     case WD_F64: return axpby_x<P_F64>(ctx, n, X, Y, py, a, b);
     case WD_F32: return axpby_x<P_F32>(ctx, n, X, Y, py, a, b);
@@ -279,18 +280,18 @@ __global__ void __launch_bounds__(RED_BLOCK) cg_xr_kernel(SiteRange X, SiteRange
         const uint32_t cb = (uint32_t)(k - h * X.Vh);
         T x[24], r[24];
         typename RealOf<PO>::T p[24], ap[24];
-        SpinorIO<PO>::load(Pp.half(h), X.Vh, cb, p);
-        SpinorIO<PO>::load(AP.half(h), X.Vh, cb, ap);
-        SpinorIO<PA>::load(X.half(h), X.Vh, cb, x);
-        SpinorIO<PA>::load(R.half(h), X.Vh, cb, r);
+        SpinorIO<PO>::load(Pp.half(h), X.ps, cb, p);
+        SpinorIO<PO>::load(AP.half(h), X.ps, cb, ap);
+        SpinorIO<PA>::load(X.half(h), X.ps, cb, x);
+        SpinorIO<PA>::load(R.half(h), X.ps, cb, r);
 #pragma unroll
         for (int i = 0; i < 24; ++i) {
             x[i] += al * (T)p[i];
             r[i] -= al * (T)ap[i];
             acc[0] += (double)r[i] * (double)r[i];
         }
-        SpinorIO<PA>::store((char*)X.half(h), X.Vh, cb, x);
-        SpinorIO<PA>::store((char*)R.half(h), X.Vh, cb, r);
+        SpinorIO<PA>::store((char*)X.half(h), X.ps, cb, x);
+        SpinorIO<PA>::store((char*)R.half(h), X.ps, cb, r);
     }
     block_reduce<1>(acc, partials);
 }
@@ -303,12 +304,12 @@ __global__ void cg_p_kernel(SiteRange R, SiteRange Pp, long long n, double beta)
     using T = typename RealOf<PA>::T;
     T r[24];
     typename RealOf<PO>::T p[24];
-    SpinorIO<PA>::load(R.half(h), R.Vh, cb, r);
-    SpinorIO<PO>::load(Pp.half(h), R.Vh, cb, p);
+    SpinorIO<PA>::load(R.half(h), R.ps, cb, r);
+    SpinorIO<PO>::load(Pp.half(h), R.ps, cb, p);
     const T be = (T)beta;
 #pragma unroll
     for (int i = 0; i < 24; ++i) p[i] = (typename RealOf<PO>::T)(r[i] + be * (T)p[i]);
-    SpinorIO<PO>::store((char*)Pp.half(h), R.Vh, cb, p);
+    SpinorIO<PO>::store((char*)Pp.half(h), R.ps, cb, p);
 }
 
 template <int PA, int PO>
@@ -319,7 +320,7 @@ static wd_status cg_t(wd_context ctx, const Geom& g, size_t nh, void* x, void* r
     const int nblk = red_blocks(n);
     WD_TRY(ensure_reduction(ctx, (size_t)nblk));
     const size_t ha = half_bytes(g, PA), ho = half_bytes(g, PO);
-    SiteRange X{(const char*)x, g.Vh, ha}, R{(const char*)r, g.Vh, ha}, Pp{(const char*)p, g.Vh, ho}, AP{(const char*)ap, g.Vh, ho};
+    SiteRange X{(const char*)x, g.Vh, g.ps, ha}, R{(const char*)r, g.Vh, g.ps, ha}, Pp{(const char*)p, g.Vh, g.ps, ho}, AP{(const char*)ap, g.Vh, g.ps, ho};
     hipLaunchKernelGGL((cg_xr_kernel<PA, PO>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, X, R, Pp, AP, n, alpha,
                        ctx->partials);
     WD_LAUNCHED();
@@ -340,7 +341,7 @@ wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nh, int pacc, void* x
 wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nh, int pacc, const void* r, int pop, void* p, double beta)
 {
     const long long n = (long long)nh * g.Vh;
-    SiteRange R{(const char*)r, g.Vh, half_bytes(g, pacc)}, Pp{(const char*)p, g.Vh, half_bytes(g, pop)};
+    SiteRange R{(const char*)r, g.Vh, g.ps, half_bytes(g, pacc)}, Pp{(const char*)p, g.Vh, g.ps, half_bytes(g, pop)};
     if (pacc == WD_F64 && pop == WD_F64)
         hipLaunchKernelGGL((cg_p_kernel<P_F64, P_F64>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
     else if (pacc == WD_F32 && pop == WD_F32)
@@ -366,14 +367,14 @@ __global__ void __launch_bounds__(RED_BLOCK) xmy_norm_kernel(SiteRange B, SiteRa
         const long long h = k / B.Vh;
         const uint32_t cb = (uint32_t)(k - h * B.Vh);
         double b[24], y[24];
-        SpinorIO<P_F64>::load(B.half(h), B.Vh, cb, b);
-        SpinorIO<P_F64>::load(Y.half(h), B.Vh, cb, y);
+        SpinorIO<P_F64>::load(B.half(h), B.ps, cb, b);
+        SpinorIO<P_F64>::load(Y.half(h), B.ps, cb, y);
 #pragma unroll
         for (int i = 0; i < 24; ++i) {
             b[i] -= y[i];
             acc[0] += b[i] * b[i];
         }
-        SpinorIO<P_F64>::store((char*)R.half(h), B.Vh, cb, b);
+        SpinorIO<P_F64>::store((char*)R.half(h), B.ps, cb, b);
     }
     block_reduce<1>(acc, partials);
 }
@@ -384,7 +385,7 @@ wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b,
     const int nblk = red_blocks(n);
     WD_TRY(ensure_reduction(ctx, (size_t)nblk));
     const size_t hb = half_bytes(g, WD_F64);
-    SiteRange B{(const char*)b, g.Vh, hb}, Y{(const char*)y, g.Vh, hb}, R{(const char*)r, g.Vh, hb};
+    SiteRange B{(const char*)b, g.Vh, g.ps, hb}, Y{(const char*)y, g.Vh, g.ps, hb}, R{(const char*)r, g.Vh, g.ps, hb};
     hipLaunchKernelGGL(xmy_norm_kernel, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, Y, R, n, ctx->partials);
     WD_LAUNCHED();
     return finish(ctx, nblk, 1, fetch);
@@ -397,8 +398,8 @@ __global__ void cxpby_kernel(SiteRange X, SiteRange Y, long long n, double ar, d
     WD_SITE_LOOP(n, X.Vh)
     using T = typename RealOf<P>::T;
     T x[24], y[24];
-    SpinorIO<P>::load(X.half(h), X.Vh, cb, x);
-    SpinorIO<P>::load(Y.half(h), Y.Vh, cb, y);
+    SpinorIO<P>::load(X.half(h), X.ps, cb, x);
+    SpinorIO<P>::load(Y.half(h), Y.ps, cb, y);
     const T a0 = (T)ar, a1 = (T)ai, b0 = (T)br, b1 = (T)bi;
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
@@ -406,14 +407,14 @@ __global__ void cxpby_kernel(SiteRange X, SiteRange Y, long long n, double ar, d
         y[2 * q] = a0 * xr - a1 * xi + b0 * yr - b1 * yi;
         y[2 * q + 1] = a0 * xi + a1 * xr + b0 * yi + b1 * yr;
     }
-    SpinorIO<P>::store((char*)Y.half(h), Y.Vh, cb, y);
+    SpinorIO<P>::store((char*)Y.half(h), Y.ps, cb, y);
 }
 
 wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nh, int prec, double ar, double ai, const void* x, double br,
                      double bi, void* y)
 {
     const long long n = (long long)nh * g.Vh;
-    SiteRange X{(const char*)x, g.Vh, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, half_bytes(g, prec)};
+    SiteRange X{(const char*)x, g.Vh, g.ps, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
     case WD_F64: hipLaunchKernelGGL(cxpby_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
     case WD_F32: hipLaunchKernelGGL(cxpby_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
@@ -436,8 +437,8 @@ __global__ void __launch_bounds__(RED_BLOCK) mdot_kernel(SiteRange Vs, size_t vs
             const long long h = s / W.Vh;
             const uint32_t cb = (uint32_t)(s - h * W.Vh);
             typename RealOf<P>::T a[24], b[24];
-            SpinorIO<P>::load(W.half(h), W.Vh, cb, b);
-            if (i < k) SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.Vh, cb, a);
+            SpinorIO<P>::load(W.half(h), W.ps, cb, b);
+            if (i < k) SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, a);
             else {
 #pragma unroll
                 for (int q = 0; q < 24; ++q) a[q] = b[q];
@@ -465,7 +466,7 @@ wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nh, int prec, const vo
     const long long ns = (long long)nh * g.Vh;
     const int nblk = red_blocks(ns);
     WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2 * n));
-    SiteRange Vs{(const char*)V, g.Vh, half_bytes(g, prec)}, W{(const char*)w, g.Vh, half_bytes(g, prec)};
+    SiteRange Vs{(const char*)V, g.Vh, g.ps, half_bytes(g, prec)}, W{(const char*)w, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
     case WD_F64: hipLaunchKernelGGL(mdot_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, (int)with_norm, W, ns, ctx->partials); break;
     case WD_F32: hipLaunchKernelGGL(mdot_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, (int)with_norm, W, ns, ctx->partials); break;
@@ -487,10 +488,10 @@ __global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef c
     WD_SITE_LOOP(n, W.Vh)
     using T = typename RealOf<P>::T;
     T w[24];
-    SpinorIO<P>::load(W.half(h), W.Vh, cb, w);
+    SpinorIO<P>::load(W.half(h), W.ps, cb, w);
     for (int i = 0; i < nvec; ++i) {
         T v[24];
-        SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.Vh, cb, v);
+        SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, v);
         const T cr = (T)cf.c[2 * i], ci = (T)cf.c[2 * i + 1];
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
@@ -500,7 +501,7 @@ __global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef c
     }
 #pragma unroll
     for (int q = 0; q < 24; ++q) w[q] *= (T)scale;
-    SpinorIO<P>::store((char*)O.half(h), W.Vh, cb, w);
+    SpinorIO<P>::store((char*)O.half(h), W.ps, cb, w);
 }
 
 wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
@@ -513,8 +514,8 @@ wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const v
     MaxpyCoef cf;
     for (int i = 0; i < 2 * k; ++i) cf.c[i] = (float)coef[i];
     const long long n = (long long)nh * g.Vh;
-    SiteRange Vs{(const char*)V, g.Vh, half_bytes(g, prec)}, W{(const char*)w, g.Vh, half_bytes(g, prec)},
-        O{(const char*)out, g.Vh, half_bytes(g, prec)};
+    SiteRange Vs{(const char*)V, g.Vh, g.ps, half_bytes(g, prec)}, W{(const char*)w, g.Vh, g.ps, half_bytes(g, prec)},
+        O{(const char*)out, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
     case WD_F32: hipLaunchKernelGGL(maxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, Vs, vstride, k, cf, (float)scale, W, O, n); break;
     default: set_error("maxpy: precision %d not supported (F32 only)", prec); return WD_EUNSUPPORTED;

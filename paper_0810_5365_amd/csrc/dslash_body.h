@@ -87,8 +87,8 @@ __device__ __forceinline__ void hop_load(const DslashArgs& A, uint32_t cb, const
     const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
     const int lpar = FWD ? A.par : 1 - A.par;
     const uint32_t lcb = FWD ? cb : nb;
-    if (!unit_link<MU, FWD>(A, c)) LinkIO<P, R, NT>::load(A.gauge + (size_t)(2 * MU + lpar) * gbytes, A.g.Vh, lcb, u);
-    SpinorIO<P>::load(in, A.g.Vh, nb, psi);
+    if (!unit_link<MU, FWD>(A, c)) LinkIO<P, R, NT>::load(A.gauge + (size_t)(2 * MU + lpar) * gbytes, A.g.ps, lcb, u);
+    SpinorIO<P>::load(in, A.g.ps, nb, psi);
 }
 
 // Arithmetic of direction D: project, boundary sign, colour multiply, accumulate.
@@ -143,7 +143,7 @@ template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
 __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, const int c[4], int rhs)
 {
     using T = typename RealOf<P>::T;
-    const size_t gbytes = link_site_bytes(P, R) * (size_t)A.g.Vh;
+    const size_t gbytes = link_site_bytes(P, R) * (size_t)A.g.ps;
     const char* in = A.in + rhs * A.in_stride;
     T acc[24];
 #pragma unroll
@@ -172,7 +172,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
     const T b = (T)A.b;
     if constexpr (XPAY) {
         T xv[24];
-        SpinorIO<P>::load(A.x + rhs * A.x_stride, A.g.Vh, cb, xv);
+        SpinorIO<P>::load(A.x + rhs * A.x_stride, A.g.ps, cb, xv);
         const T a = (T)A.a;
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = a * xv[k] + b * acc[k];
@@ -180,7 +180,7 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= b;
     }
-    SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.Vh, cb, acc);
+    SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.ps, cb, acc);
 }
 
 template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>

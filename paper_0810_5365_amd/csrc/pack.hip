@@ -24,7 +24,7 @@ __global__ void pack_gauge_kernel(const double* __restrict__ canon, char* __rest
     const int par = (x + y + z + t) & 1;
     const uint32_t cb = (uint32_t)(lex >> 1);
     const double* u = canon + 18 * k;
-    const int Vh = g.Vh;
+    const int Vh = g.ps;   // plane stride
     char* grp = out + (size_t)(2 * mu + par) * link_site_bytes(P, R) * Vh;
     if constexpr (P == P_F32) {
         float4* p = (float4*)grp;
@@ -86,7 +86,7 @@ __global__ void spinor_pack_kernel(double* __restrict__ canon, char* __restrict_
     if (k >= ntotal) return;
     const long long rhs = k / nsites_per_rhs;
     const long long s = k - rhs * nsites_per_rhs;
-    const size_t hb = spinor_site_bytes(P) * (size_t)g.Vh;
+    const size_t hb = spinor_site_bytes(P) * (size_t)g.ps;
     int par;
     uint32_t cb;
     char* base;
@@ -106,11 +106,11 @@ __global__ void spinor_pack_kernel(double* __restrict__ canon, char* __restrict_
     double* c = canon + 24 * k;
     T v[24];
     if constexpr (UNPACK) {
-        SpinorIO<P>::load(base, g.Vh, cb, v);
+        SpinorIO<P>::load(base, g.ps, cb, v);
         for (int i = 0; i < 24; ++i) c[i] = (double)v[i];
     } else {
         for (int i = 0; i < 24; ++i) v[i] = (T)c[i];
-        SpinorIO<P>::store(base, g.Vh, cb, v);
+        SpinorIO<P>::store(base, g.ps, cb, v);
     }
 }
 
@@ -147,7 +147,7 @@ wd_status launch_spinor_pack(wd_context ctx, const Geom& g, int subset, int prec
 
 // ---- precision conversion between packed fields --------------------------------
 template <int SP, int DP>
-__global__ void convert_kernel(const char* __restrict__ src, char* __restrict__ dst, int Vh, long long nsites)
+__global__ void convert_kernel(const char* __restrict__ src, char* __restrict__ dst, int Vh, int ps, long long nsites)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsites) return;
@@ -155,9 +155,9 @@ __global__ void convert_kernel(const char* __restrict__ src, char* __restrict__ 
     const uint32_t cb = (uint32_t)(k - h * Vh);
     typename RealOf<SP>::T v[24];
     typename RealOf<DP>::T w[24];
-    SpinorIO<SP>::load(src + (size_t)h * spinor_site_bytes(SP) * Vh, Vh, cb, v);
+    SpinorIO<SP>::load(src + (size_t)h * spinor_site_bytes(SP) * ps, ps, cb, v);
     for (int i = 0; i < 24; ++i) w[i] = (typename RealOf<DP>::T)v[i];
-    SpinorIO<DP>::store(dst + (size_t)h * spinor_site_bytes(DP) * Vh, Vh, cb, w);
+    SpinorIO<DP>::store(dst + (size_t)h * spinor_site_bytes(DP) * ps, ps, cb, w);
 }
 
 template <int SP, int DP>
@@ -166,7 +166,7 @@ static wd_status convert_t(wd_context ctx, const Geom& g, size_t nhalves, const 
     const long long n = (long long)nhalves * g.Vh;
     const int bs = 256;
     hipLaunchKernelGGL((convert_kernel<SP, DP>), dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, ctx->stream,
-                       (const char*)src, (char*)dst, g.Vh, n);
+                       (const char*)src, (char*)dst, g.Vh, g.ps, n);
     WD_LAUNCHED();
     return WD_OK;
 }

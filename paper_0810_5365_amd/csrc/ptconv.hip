@@ -17,7 +17,8 @@
 //             reduction done per path with float64 partial sums.
 //
 // Packed feature layout (float32): sample n, channel c, parity par, colour k,
-// site cb -> float2 at (((n C + c) 2 + par) 3 + k) Vh + cb.
+// site cb -> float2 at (((n C + c) 2 + par) 3 + k) Vh + cb (no plane padding: features are
+// ordinary tensors that losses reduce over as a whole).
 #include <stdlib.h>
 
 #include "wd_core.h"
@@ -108,7 +109,7 @@ __device__ __forceinline__ void ptconv_dir(const PTArgs& A, const float2* in, in
     const int lpar = FWD ? par : 1 - par;
     const uint32_t lcb = FWD ? cb : nb;
     float u[18];
-    LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.Vh, A.g.Vh, lcb, u);
+    LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps, A.g.ps, lcb, u);
     const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
     mix_path<COUT, WP>(A, FWD ? 1 + MU : 5 + MU, in, 1 - par, nb, u, !FWD, sign, true, acc);
 }
@@ -212,7 +213,7 @@ __global__ void __launch_bounds__(256) ptconv_wgrad_kernel(PTArgs A, const float
                 const int lpar = fwd ? par : 1 - par;
                 const uint32_t lcb = fwd ? cb : nb;
                 float u[18], v[6];
-                LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * mu + lpar) * link_site_bytes(P_F32, R) * Vh, Vh, lcb, u);
+                LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * mu + lpar) * link_site_bytes(P_F32, R) * A.g.ps, A.g.ps, lcb, u);
 #pragma unroll
                 for (int kk = 0; kk < 3; ++kk) {
                     const float2 q = in[fidx(b, 1 - par, kk, Vh, nb)];
@@ -275,7 +276,7 @@ __global__ void wgrad_finish_kernel(const double* __restrict__ partials, int nbl
 }
 
 // ---- spinor (float32 packed) <-> 4-channel features ----------------------------
-__global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh, int nsamples, bool to_features)
+__global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh, int ps, int nsamples, bool to_features)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 2ll * Vh * nsamples) return;
@@ -283,12 +284,12 @@ __global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh,
     const uint32_t idx = (uint32_t)(k - (long long)n * 2 * Vh);
     const int par = idx >= (uint32_t)Vh ? 1 : 0;
     const uint32_t cb = idx - (uint32_t)par * Vh;
-    const size_t hb = spinor_site_bytes(P_F32) * (size_t)Vh;
+    const size_t hb = spinor_site_bytes(P_F32) * (size_t)ps;
     char* sp = (char*)spinor + ((size_t)n * 2 + par) * hb;
     float2* f = feat + (size_t)n * 4 * 2 * 3 * Vh;
     float v[24];
     if (to_features) {
-        SpinorIO<P_F32>::load(sp, Vh, cb, v);
+        SpinorIO<P_F32>::load(sp, ps, cb, v);
         for (int s = 0; s < 4; ++s)
             for (int c = 0; c < 3; ++c) f[fidx(s, par, c, Vh, cb)] = make_float2(v[(s * 3 + c) * 2], v[(s * 3 + c) * 2 + 1]);
     } else {
@@ -298,7 +299,7 @@ __global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh,
                 v[(s * 3 + c) * 2] = q.x;
                 v[(s * 3 + c) * 2 + 1] = q.y;
             }
-        SpinorIO<P_F32>::store(sp, Vh, cb, v);
+        SpinorIO<P_F32>::store(sp, ps, cb, v);
     }
 }
 
@@ -360,7 +361,7 @@ __device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int 
         constexpr bool FWD = PATH <= 4;
         const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
         const int lpar = FWD ? par : 1 - par;
-        LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * Vh, Vh,
+        LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps, A.g.ps,
                                       FWD ? cb : nb, u);
         sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
         src = nb;
@@ -536,7 +537,7 @@ wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, vo
 {
     const long long n = 2ll * g.Vh * nsamples;
     hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
-                       (const char*)spinor, (float2*)feat, g.Vh, nsamples, to_features);
+                       (const char*)spinor, (float2*)feat, g.Vh, g.ps, nsamples, to_features);
     WD_LAUNCHED();
     return WD_OK;
 }

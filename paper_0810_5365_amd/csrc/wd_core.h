@@ -55,8 +55,8 @@ inline bool valid_prec(int p) { return p >= WD_F64 && p <= WD_BF16; }
 inline bool valid_subset(int s) { return s >= WD_FULL && s <= WD_ODD; }
 inline bool valid_recon(int r) { return r == WD_RECON_12 || r == WD_RECON_18; }
 
-// Bytes of one half field (Vh sites of one parity, one rhs) at precision p.
-inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (size_t)g.Vh; }
+// Bytes of one half field (Vh sites of one parity in planes ps apart, one rhs) at precision p.
+inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (size_t)g.ps; }
 inline size_t halves_of(int subset, int nrhs) { return (size_t)nrhs * (subset == WD_FULL ? 2 : 1); }
 
 wd_status make_geom(const wd_lattice* lat, Geom* g);

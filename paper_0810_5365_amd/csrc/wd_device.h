@@ -43,6 +43,7 @@ struct Geom {
     int L[4];          // X, Y, Z, T
     int Xh;            // X / 2
     int Vh;            // sites per parity
+    int ps;            // plane stride in sites (Vh, padded on large lattices)
     int st[4];         // checkerboard-index stride of a unit step in mu (st[0] unused)
     float bcf[4];      // boundary sign per direction
     double bcd[4];
@@ -134,7 +135,20 @@ template <int P> __device__ __forceinline__ uint32_t pack2(float a, float b)
 }
 
 // ---------------------------------------------------------------------------
-// Spinor half-field access.  A half field holds the Vh sites of one parity:
+// Plane stride.  On a lattice of 2^k sites every plane of a packed field
+// would start a power of two bytes after the previous one, so the same site
+// of all planes maps onto the same HBM channels and the streams of one
+// kernel queue behind each other.  Large lattices therefore space planes
+// ps = roundup(Vh, 64) + 256 sites apart (the tail of each plane is unused
+// padding); below 4096 sites per parity ps = Vh.
+__host__ __device__ constexpr long long plane_stride(long long Vh)
+{
+    return Vh < 4096 ? Vh : ((Vh + 63) / 64) * 64 + 256;
+}
+
+// ---------------------------------------------------------------------------
+// Spinor half-field access.  A half field holds the Vh sites of one parity
+// in planes ps sites apart (the stride argument of load and store):
 //   F32 : 6 planes of float4            (96 B/site)
 //   F64 : 12 planes of double2          (192 B/site)
 //   F16/BF16: 3 planes of 8 x 16-bit + 1 plane of float32 scales (52 B/site)
@@ -220,7 +234,7 @@ __host__ __device__ constexpr size_t spinor_site_bytes(int P)
 
 // ---------------------------------------------------------------------------
 // Link access.  Links are grouped by (mu, parity of the site they start at);
-// each group holds Vh links as structure-of-arrays planes:
+// each group holds Vh links as structure-of-arrays planes ps sites apart:
 //   F32 r12: 3 x float4         r18: 4 x float4 + 1 x float2
 //   F64 r12: 6 x double2        r18: 9 x double2
 //   16-bit r12: uint4 + uint2   r18: 2 x uint4 + 1 x uint32

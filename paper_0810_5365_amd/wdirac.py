@@ -73,6 +73,7 @@ _PROTOS = {
     "wd_gauge_destroy": ("status", [_V]),
     "wd_gauge_fix_temporal": ("status", [_V, _V]),
     "wd_spinor_bytes": (_S, [_P(WdLattice), _I, _I, _I]),
+    "wd_plane_stride": (ctypes.c_longlong, [_P(WdLattice)]),
     "wd_spinor_pack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),
     "wd_spinor_unpack": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V]),
     "wd_spinor_convert": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _I, _V]),
@@ -227,6 +228,10 @@ class Gauge:
 
 def spinor_bytes(lat, subset, prec, nrhs=1):
     return int(wd_spinor_bytes(ctypes.byref(lat), int(subset), int(prec), int(nrhs)))
+
+
+def plane_stride(lat):
+    return int(wd_plane_stride(ctypes.byref(lat)))
 
 
 def new_field(lat, subset, prec, nrhs=1, device=0):

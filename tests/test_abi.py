@@ -45,13 +45,27 @@ def test_abi_version_and_status_strings(w):
     assert b"unknown" in w.wd_status_string(99)
 
 
+def test_plane_stride(w):
+    # below 4096 sites per parity the planes are contiguous
+    assert w.plane_stride(w.lattice((4, 4, 4, 4))) == 128
+    assert w.plane_stride(w.lattice((6, 6, 6, 6))) == 648
+    assert w.plane_stride(w.lattice((8, 8, 8, 14))) == 3584
+    # above: rounded up to 64 sites, plus 256, never a power of two
+    assert w.plane_stride(w.lattice((8, 8, 8, 16))) == 4096 + 256
+    assert w.plane_stride(w.lattice((32, 32, 32, 64))) == (1 << 20) + 256
+    assert w.plane_stride(w.lattice((6, 6, 6, 40))) == 4352 + 256   # V/2 = 4320 -> 4352
+    assert w.plane_stride(w.lattice((7, 8, 8, 16))) == 0
+
+
 def test_spinor_bytes(w):
     lat = w.lattice((8, 8, 8, 16))
-    Vh = 8 * 8 * 8 * 16 // 2
-    assert w.spinor_bytes(lat, w.EVEN, w.F32) == 96 * Vh
-    assert w.spinor_bytes(lat, w.ODD, w.F64) == 192 * Vh
-    assert w.spinor_bytes(lat, w.FULL, w.BF16) == 2 * 52 * Vh
-    assert w.spinor_bytes(lat, w.FULL, w.F16, 3) == 3 * 2 * 52 * Vh
+    ps = 8 * 8 * 8 * 16 // 2 + 256
+    assert w.spinor_bytes(lat, w.EVEN, w.F32) == 96 * ps
+    assert w.spinor_bytes(lat, w.ODD, w.F64) == 192 * ps
+    assert w.spinor_bytes(lat, w.FULL, w.BF16) == 2 * 52 * ps
+    assert w.spinor_bytes(lat, w.FULL, w.F16, 3) == 3 * 2 * 52 * ps
+    small = w.lattice((4, 4, 4, 8))
+    assert w.spinor_bytes(small, w.FULL, w.F32) == 2 * 96 * 256
     # bad input -> 0
     assert w.spinor_bytes(w.lattice((7, 8, 8, 16)), w.EVEN, w.F32) == 0
     assert w.spinor_bytes(w.lattice((0, 8, 8, 16)), w.EVEN, w.F32) == 0
