@@ -172,14 +172,20 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
     out = {"lattice": list(dims), "eps": eps, "kappa": kappa, "tol": tol}
     runs = [("f64", w.F64, False), ("f32", w.F32, False), ("f16", w.F16, False), ("bf16", w.BF16, False),
             ("pure_f32", w.F32, True)]
+    default_delta = {w.F32: 1e-3, w.F16: 1e-2, w.BF16: 3e-2}   # the library's defaults (delta < 0)
     for name, p, pure in runs:
-        fx = torch.zeros_like(fb)
-        prm = w.solver_params(tol=tol, maxiter=5000, sloppy=p, delta=0.1, pure_sloppy=pure)
-        info = w.WdSolverInfo()
-        w.wd_wilson_solve(g.handle, kappa, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
-                          ok=(w.WD_OK, w.WD_ENOCONV))
+        secs = []
+        for rep in range(2):   # the first solve of a precision also sizes the workspace
+            fx = torch.zeros_like(fb)
+            prm = w.solver_params(tol=tol, maxiter=5000, sloppy=p, delta=-1.0, pure_sloppy=pure)
+            info = w.WdSolverInfo()
+            w.wd_wilson_solve(g.handle, kappa, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
+                              ok=(w.WD_OK, w.WD_ENOCONV))
+            secs.append(info.seconds)
         d = {k: v for k, v in info.as_dict().items() if k not in ("cycles", "fell_back")}
         d["seconds"] = round(d["seconds"], 5)
+        d["seconds_first"] = round(secs[0], 5)
+        d["delta"] = None if (pure or p == w.F64) else default_delta[p]
         out[name] = d
     g.close()
     return out

@@ -177,7 +177,11 @@ typedef struct {
     double tol;        /* stop when ||r|| / ||b|| <= tol (true residual, float64) */
     int maxiter;       /* iteration cap; WD_ENOCONV when reached                   */
     int sloppy;        /* wd_prec of the inner iterations (F64, F32, F16, BF16)    */
-    double delta;      /* reliable update when ||r|| < delta * max ||r|| since last */
+    double delta;      /* reliable update when ||r|| < delta * max ||r|| since last;
+                          < 0: the default for the sloppy precision (F32 1e-3,
+                          F16 1e-2, BF16 3e-2; measured on the 32^3 x 64 and
+                          16^3 x 32 solves, each ~10x above where the iteration
+                          count starts to grow)                                   */
     int pure_sloppy;   /* 1: never recompute the residual (reports the stall level) */
 } wd_solver_params;
 
@@ -270,16 +274,20 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
 
 /* ---- learned-preconditioner solve ---------------------------------------------- */
 /* Solve M x = b on the full lattice (b, x: FULL float64 packed fields; x is the
- * initial guess) by flexible GMRES with right preconditioner N, a stack of
- * nlayers parallel-transport convolutions with channel widths widths[0..nlayers]
- * (widths[0] = widths[nlayers] = 4: spin as channels) and weights[l] the
- * [9][widths[l+1]][widths[l]] complex weights at wprec (device pointers);
- * nlayers = 0 runs unpreconditioned GMRES.  Cycles of at most `restart`
- * iterations run in float32 and stop when their residual estimate has fallen
- * by params->delta; x and the true residual b - M x are updated in float64
- * after each cycle, and the solve ends when ||b - M x|| / ||b|| <= params->tol.
- * A NaN or a cycle that reduces the true residual less than tenfold hands x
- * to wd_wilson_solve (fell_back = 1), whose float64 residual is reported.
+ * initial guess).  The Krylov iteration is flexible GMRES on the even-odd Schur
+ * complement Mhat (paper Section 4), right-preconditioned by the even-even block
+ * of a network N ~ M^-1: K v_e = [N (v_e, 0)]_e, exact if N = M^-1.  N is a
+ * stack of nlayers parallel-transport convolutions with channel widths
+ * widths[0..nlayers] (widths[0] = widths[nlayers] = 4: spin as channels) and
+ * weights[l] the [9][widths[l+1]][widths[l]] complex weights at wprec (device
+ * pointers); nlayers = 0 runs unpreconditioned GMRES on Mhat.  Cycles of at
+ * most `restart` iterations run in float32 on rhat_e = r_e + kappa D_eo r_o and
+ * stop when their residual estimate has fallen by params->delta (> 0; else
+ * 1e-4); x (both parities) and the true residual b - M x are updated in
+ * float64 after each cycle, and the solve ends when ||b - M x|| / ||b|| <=
+ * params->tol.  A NaN or a cycle that reduces the true residual less than
+ * tenfold hands x to wd_wilson_solve (fell_back = 1), whose float64 residual
+ * is reported.
  * restart must be in [1, 63].  Synchronous. */
 wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
                           const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,

@@ -19,6 +19,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
     const int ps = prm.sloppy == WD_F64 ? WD_F64 : WD_F32;
+    const double delta = resolve_delta(prm.delta, ps);
     const size_t hs = half_bytes(G, ps), h64 = half_bytes(G, WD_F64);
     void *r, *t64, *rs, *r0, *p, *v, *s, *t, *xs;
     WD_TRY(ws_get(ctx, "bicg.r", h64, &r));
@@ -96,7 +97,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
             status = WD_ENAN;
             break;
         }
-        if (rr_s <= target || rr_s < prm.delta * prm.delta * maxrr) {
+        if (rr_s <= target || rr_s < delta * delta * maxrr) {
             WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
             WD_TRY(blas_zero(ctx, G, 1, ps, xs));
             dirty = false;
@@ -130,8 +131,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
         set_error("wd_bicgstab_solve: NULL argument");
         return WD_EINVAL;
     }
-    if (!(params->tol > 0.0) || params->maxiter < 0 || !valid_prec(params->sloppy) || params->delta < 0.0 ||
-        params->delta >= 1.0) {
+    if (!(params->tol > 0.0) || params->maxiter < 0 || !valid_prec(params->sloppy) || !(params->delta < 1.0)) {
         set_error("wd_bicgstab_solve: bad solver params");
         return WD_EINVAL;
     }

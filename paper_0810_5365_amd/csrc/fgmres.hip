@@ -1,16 +1,22 @@
-// Flexible GMRES on the full Wilson system M x = b with a right
-// preconditioner that may change from one iteration to the next (Saad,
-// "A flexible inner-outer preconditioned GMRES algorithm", SISC 1993): here the
-// learned parallel-transport network N ~ M^-1.
+// Flexible GMRES for the Wilson system M x = b with a right preconditioner
+// that may change from one iteration to the next (Saad, "A flexible
+// inner-outer preconditioned GMRES algorithm", SISC 1993).  The Krylov
+// iteration runs on the even-odd Schur complement Mhat = 1 - kappa^2 D_eo D_oe
+// (paper Section 4), whose inverse is exactly the even-even block of M^-1.
+// So the learned parallel-transport network N ~ M^-1, applied to (v_e, 0),
+// gives the preconditioner K v_e = [N (v_e, 0)]_e ~ Mhat^-1 v_e.
 //
-// Mixed precision by iterative refinement: each cycle solves M e = r in
-// float32 (operator, network, Krylov basis) from e = 0 for at most `restart`
-// iterations or until the cycle's residual estimate falls by the factor
-// params->delta; then x += e in float64 and r = b - M x is recomputed in
-// float64, which decides convergence.  Orthogonalisation is classical
-// Gram-Schmidt applied twice (one fused multi-dot and one fused multi-axpy
-// per pass).  The plain solver is the fallback: a NaN, or a cycle that fails
-// to reduce the true residual tenfold, hands x to the even-odd CG
+// Mixed precision by iterative refinement on the full system: r = b - M x in
+// float64; rhat_e = r_e + kappa D_eo r_o; one float32 cycle (operator,
+// network, Krylov basis) solves Mhat e_e = rhat_e from zero for at most
+// `restart` iterations or until its residual estimate falls by
+// params->delta; then x_e += e_e, x_o += r_o + kappa D_oe e_e in float64 (the
+// odd rows of the update are exact, the even rows leave rhat_e - Mhat e_e),
+// and r is recomputed in float64, which decides convergence.
+// Orthogonalisation is classical Gram-Schmidt with a second pass when the
+// first removed most of the vector (one fused multi-dot and one fused
+// multi-axpy per pass).  The plain solver is the fallback: a NaN, or a cycle
+// that fails to reduce the true residual tenfold, hands x to the even-odd CG
 // (wd_wilson_solve), which then finishes the solve.
 #include <chrono>
 #include <cmath>
@@ -31,19 +37,19 @@ struct Net {
     int wprec;
 };
 
-// z = N v on float32 FULL spinor fields (4 channels in and out)
+// z_e = [N (v_e, 0)]_e on float32 EVEN half fields (4 channels in and out)
 static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, void* fa, void* fb)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
-    WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true));
+    WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true, true));
     void* cur = fa;
     void* nxt = fb;
     for (int l = 0; l < net.nlayers; ++l) {
         WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1));
         std::swap(cur, nxt);
     }
-    return launch_spinor_features(ctx, G, 1, z, cur, false);
+    return launch_spinor_features(ctx, G, 1, z, cur, false, true);
 }
 
 static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& prm, int m, const Net* net, const void* b,
@@ -51,16 +57,18 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
-    const size_t nh = 2;   // FULL fields
-    const size_t v32 = half_bytes(G, WD_F32) * nh;
-    const size_t v64 = half_bytes(G, WD_F64) * nh;
-    void *V, *Z, *wv, *e, *r, *t, *fa = nullptr, *fb = nullptr;
+    const size_t nh = 1;   // Krylov vectors: EVEN half fields
+    const size_t v32 = half_bytes(G, WD_F32);
+    const size_t h64 = half_bytes(G, WD_F64);
+    void *V, *Z, *wv, *e, *e64, *rhat, *r, *t, *fa = nullptr, *fb = nullptr;
     WD_TRY(ws_get(ctx, "fgmres.V", v32 * (m + 1), &V));
     WD_TRY(ws_get(ctx, "fgmres.Z", v32 * m, &Z));
     WD_TRY(ws_get(ctx, "fgmres.w", v32, &wv));
     WD_TRY(ws_get(ctx, "fgmres.e", v32, &e));
-    WD_TRY(ws_get(ctx, "fgmres.r", v64, &r));
-    WD_TRY(ws_get(ctx, "fgmres.t", v64, &t));
+    WD_TRY(ws_get(ctx, "fgmres.e64", h64, &e64));
+    WD_TRY(ws_get(ctx, "fgmres.rhat", h64, &rhat));
+    WD_TRY(ws_get(ctx, "fgmres.r", 2 * h64, &r));
+    WD_TRY(ws_get(ctx, "fgmres.t", 2 * h64, &t));
     if (net) {
         int cmax = 0;
         for (int c : net->widths) cmax = c > cmax ? c : cmax;
@@ -70,8 +78,12 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     }
     auto Vi = [&](int i) { return (void*)((char*)V + (size_t)i * v32); };
     auto Zi = [&](int i) { return (void*)((char*)Z + (size_t)i * v32); };
+    char* x_e = (char*)x;
+    char* x_o = x_e + h64;
+    const char* r_e = (const char*)r;
+    const char* r_o = r_e + h64;
 
-    WD_TRY(blas_norm2(ctx, G, nh, WD_F64, b, true));
+    WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
     const double bb = ctx->hres[0];
     const double tol2 = prm.tol * prm.tol * bb;
     info->iters = 0;
@@ -81,13 +93,13 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     info->fell_back = 0;
     *fallback = false;
     if (!(bb > 0.0)) {
-        WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
+        WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
         info->true_resid = info->true_resid_M = 0.0;
         return WD_OK;
     }
     auto true_res = [&](double* rr) -> wd_status {
         WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
-        WD_TRY(blas_xmy_norm(ctx, G, nh, b, t, r, true));
+        WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
         *rr = ctx->hres[0];
         info->operator_applies++;
         return WD_OK;
@@ -96,12 +108,14 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     WD_TRY(true_res(&rr));
     const double inner = prm.delta > 0.0 ? prm.delta : 1e-4;
     while (rr > tol2 && info->iters < prm.maxiter) {
-        // ---- one float32 cycle on M e = r -----------------------------------------
-        // stop the cycle at delta, or earlier if that already meets the requested tolerance
-        const double cycle_tol = std::max(inner, 0.5 * std::sqrt(tol2 / rr));
-        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, WD_F32, Vi(0)));
+        // ---- one float32 cycle on Mhat e_e = rhat_e --------------------------------
+        // rhat_e = r_e + kappa D_eo r_o; the updated full residual equals rhat_e - Mhat e_e,
+        // so stop at delta, or earlier if that already meets the requested tolerance
+        WD_TRY(hop_half(g, WD_F64, 0, 0, 1, r_o, (long long)h64, rhat, (long long)h64, r_e, (long long)h64, 1.0, kappa));
+        WD_TRY(launch_convert(ctx, G, nh, WD_F64, rhat, WD_F32, Vi(0)));
         WD_TRY(blas_norm2(ctx, G, nh, WD_F32, Vi(0), true));
         const double beta = std::sqrt(ctx->hres[0]);
+        const double cycle_tol = std::max(inner, 0.5 * std::sqrt(tol2) / beta);
         if (!std::isfinite(beta) || beta == 0.0) {
             *fallback = !std::isfinite(beta);
             break;
@@ -114,7 +128,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         bool bad = false;
         for (; j < m && info->iters < prm.maxiter; ++j) {
             if (net) WD_TRY(apply_net(g, *net, Vi(j), Zi(j), fa, fb));
-            WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F32, 1, net ? Zi(j) : Vi(j), wv));
+            WD_TRY(op_M(g, kappa, WD_EVEN, 0, WD_F32, 1, net ? Zi(j) : Vi(j), wv));
             info->operator_applies++;
             info->iters++;
             // classical Gram-Schmidt with the norm in the same reduction; a second pass only when
@@ -202,7 +216,11 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
             const int k = j - i0 < WD_MAXPY ? j - i0 : WD_MAXPY;
             WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, net ? Zi(i0) : Vi(i0), v32, k, coef.data() + 2 * i0, e, 1.0, e));
         }
-        WD_TRY(blas_axpby(ctx, G, nh, WD_F32, e, 1.0, WD_F64, x, 1.0));
+        // x_e += e_e ; x_o += r_o + kappa D_oe e_e   (float64)
+        WD_TRY(launch_convert(ctx, G, nh, WD_F32, e, WD_F64, e64));
+        WD_TRY(blas_axpby(ctx, G, nh, WD_F64, e64, 1.0, WD_F64, x_e, 1.0));
+        WD_TRY(hop_half(g, WD_F64, 1, 0, 1, e64, (long long)h64, rhat, (long long)h64, r_o, (long long)h64, 1.0, kappa));
+        WD_TRY(blas_axpby(ctx, G, nh, WD_F64, rhat, 1.0, WD_F64, x_o, 1.0));
         const double rr_prev = rr;
         WD_TRY(true_res(&rr));
         info->reliable_updates++;
@@ -268,7 +286,7 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
         const int done = info->iters;
         wd_solver_params p2 = *params;
         p2.maxiter = params->maxiter - done > 0 ? params->maxiter - done : 1;
-        if (p2.delta <= 0.0 || p2.delta >= 1.0) p2.delta = 0.1;
+        if (p2.delta == 0.0 || !(p2.delta < 1.0)) p2.delta = -1.0;   // the plain solver's default
         if (p2.sloppy == WD_F64 || p2.sloppy > WD_BF16) p2.sloppy = WD_F32;
         s = wd_wilson_solve(g, kappa, &p2, b, x, &ci);
         info->iters += ci.iters;

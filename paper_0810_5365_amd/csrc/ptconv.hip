@@ -50,6 +50,8 @@ template <int WP> __device__ __forceinline__ float2 load_w(const void* W, int i)
     }
 }
 
+// w = U v or U^dagger v for a 3x3 complex U (row-major re, im pairs), as chains of
+// fused multiply-adds.
 template <typename T> __device__ __forceinline__ void mat_vec(const T* u, const T* v, T* w, bool dag)
 {
 #pragma unroll
@@ -59,8 +61,10 @@ template <typename T> __device__ __forceinline__ void mat_vec(const T* u, const 
         for (int b = 0; b < 3; ++b) {
             const int e = dag ? (3 * b + a) : (3 * a + b);
             const T ur = u[2 * e], ui = dag ? -u[2 * e + 1] : u[2 * e + 1];
-            re += ur * v[2 * b] - ui * v[2 * b + 1];
-            im += ur * v[2 * b + 1] + ui * v[2 * b];
+            re = fma(ur, v[2 * b], re);
+            re = fma(-ui, v[2 * b + 1], re);
+            im = fma(ur, v[2 * b + 1], im);
+            im = fma(ui, v[2 * b], im);
         }
         w[2 * a] = re;
         w[2 * a + 1] = im;
@@ -276,7 +280,9 @@ __global__ void wgrad_finish_kernel(const double* __restrict__ partials, int nbl
 }
 
 // ---- spinor (float32 packed) <-> 4-channel features ----------------------------
-__global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh, int ps, int nsamples, bool to_features)
+// even_only: the spinor is one EVEN half field; odd sites read as zero and are not written.
+__global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh, int ps, int nsamples, bool to_features,
+                                       bool even_only)
 {
     const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= 2ll * Vh * nsamples) return;
@@ -285,14 +291,20 @@ __global__ void spinor_features_kernel(const char* spinor, float2* feat, int Vh,
     const int par = idx >= (uint32_t)Vh ? 1 : 0;
     const uint32_t cb = idx - (uint32_t)par * Vh;
     const size_t hb = spinor_site_bytes(P_F32) * (size_t)ps;
-    char* sp = (char*)spinor + ((size_t)n * 2 + par) * hb;
+    char* sp = (char*)spinor + (even_only ? (size_t)n * hb : ((size_t)n * 2 + par) * hb);
     float2* f = feat + (size_t)n * 4 * 2 * 3 * Vh;
     float v[24];
     if (to_features) {
-        SpinorIO<P_F32>::load(sp, ps, cb, v);
+        if (even_only && par == 1) {
+#pragma unroll
+            for (int i = 0; i < 24; ++i) v[i] = 0.f;
+        } else {
+            SpinorIO<P_F32>::load(sp, ps, cb, v);
+        }
         for (int s = 0; s < 4; ++s)
             for (int c = 0; c < 3; ++c) f[fidx(s, par, c, Vh, cb)] = make_float2(v[(s * 3 + c) * 2], v[(s * 3 + c) * 2 + 1]);
     } else {
+        if (even_only && par == 1) return;
         for (int s = 0; s < 4; ++s)
             for (int c = 0; c < 3; ++c) {
                 const float2 q = f[fidx(s, par, c, Vh, cb)];
@@ -344,6 +356,14 @@ __global__ void feature_pack_kernel(double* canon, float2* feat, Geom g, int C, 
 // B[4 (l / 16) + q][l % 16] and D[4 (l / 16) + q][l % 16] for q = 0..3.
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// Two floats -> packed bf16 pair, round to nearest even, in one conversion instruction.
+__device__ __forceinline__ uint32_t cvt_bf16x2(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2_t{a, b}, bf16x2_t));
+}
 constexpr int MF_LD = 20;   // bf16 per staged column: 16 K values + 4 of padding (40 B, conflict-free reads)
 
 template <int PATH, int R, int CIN>
@@ -354,7 +374,6 @@ __device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int 
     float u[18];
     uint32_t src = cb;
     int spar = par;
-    float sign = 1.f;
     bool dag = false;
     if constexpr (PATH > 0) {
         constexpr int MU = (PATH - 1) & 3;
@@ -363,31 +382,34 @@ __device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int 
         const int lpar = FWD ? par : 1 - par;
         LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps, A.g.ps,
                                       FWD ? cb : nb, u);
-        sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
+        // boundary sign folded into the (reconstructed) link: 18 products instead of 6 C_in
+        const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) u[i] *= sign;
         src = nb;
         spar = 1 - par;
         dag = !FWD;
     }
+    // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
+    const float2* site = in + (size_t)spar * 3 * Vh + src;
 #pragma unroll
     for (int b = 0; b < CIN; ++b) {
         float v[6], t[6];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float2 q = in[fidx(b, spar, k, Vh, src)];
+            const float2 q = site[(size_t)(b * 6 + k) * Vh];
             v[2 * k] = q.x;
             v[2 * k + 1] = q.y;
         }
         if constexpr (PATH > 0) {
             mat_vec(u, v, t, dag);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) t[i] *= sign;
         } else {
 #pragma unroll
             for (int i = 0; i < 6; ++i) t[i] = v[i];
         }
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = pack2<P_BF16>(t[2 * k], t[2 * k + 1]);
+            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(t[2 * k], t[2 * k + 1]);
     }
 }
 
@@ -533,11 +555,11 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
 }
 
 wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, void* spinor, void* feat,
-                                 bool to_features)
+                                 bool to_features, bool even_only)
 {
     const long long n = 2ll * g.Vh * nsamples;
     hipLaunchKernelGGL(spinor_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, ctx->stream,
-                       (const char*)spinor, (float2*)feat, g.Vh, g.ps, nsamples, to_features);
+                       (const char*)spinor, (float2*)feat, g.Vh, g.ps, nsamples, to_features, even_only);
     WD_LAUNCHED();
     return WD_OK;
 }

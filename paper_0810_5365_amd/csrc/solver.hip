@@ -53,7 +53,8 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     const int pacc = pop == WD_F64 ? WD_F64 : WD_F32;
     const size_t nh = halves_of(P.subset, 1);
     const bool pure = prm.pure_sloppy != 0;
-    const bool use_delta = pop != WD_F64 && prm.delta > 0.0;
+    const double delta = resolve_delta(prm.delta, pop);
+    const bool use_delta = pop != WD_F64 && delta > 0.0;
 
     void *r, *rs, *xs, *p, *ap;
     WD_TRY(ws_get(ctx, "cg.r", half_bytes(G, WD_F64) * nh, &r));
@@ -115,7 +116,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
             }
             if (pure) {
                 if (rr_new <= trigger) break;
-            } else if ((use_delta && rr_new < prm.delta * prm.delta * maxrr) || rr_new <= trigger) {
+            } else if ((use_delta && rr_new < delta * delta * maxrr) || rr_new <= trigger) {
                 // reliable update: fold the sloppy solution into x and recompute r in float64
                 WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
                 WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
@@ -157,7 +158,7 @@ static wd_status check_params(const wd_solver_params* prm)
         set_error("solver params are NULL");
         return WD_EINVAL;
     }
-    if (!(prm->tol > 0.0) || prm->maxiter < 0 || !valid_prec(prm->sloppy) || prm->delta < 0.0 || prm->delta >= 1.0) {
+    if (!(prm->tol > 0.0) || prm->maxiter < 0 || !valid_prec(prm->sloppy) || !(prm->delta < 1.0)) {
         set_error("bad solver params: tol %g, maxiter %d, sloppy %d, delta %g", prm->tol, prm->maxiter, prm->sloppy,
                   prm->delta);
         return WD_EINVAL;

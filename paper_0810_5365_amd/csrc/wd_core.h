@@ -57,6 +57,12 @@ inline bool valid_recon(int r) { return r == WD_RECON_12 || r == WD_RECON_18; }
 
 // Bytes of one half field (Vh sites of one parity in planes ps apart, one rhs) at precision p.
 inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (size_t)g.ps; }
+// Reliable-update threshold: delta < 0 selects the default for the sloppy precision.
+inline double default_delta(int prec)
+{
+    return prec == WD_F32 ? 1e-3 : (prec == WD_F16 ? 1e-2 : (prec == WD_BF16 ? 3e-2 : 0.1));
+}
+inline double resolve_delta(double delta, int prec) { return delta < 0.0 ? default_delta(prec) : delta; }
 inline size_t halves_of(int subset, int nrhs) { return (size_t)nrhs * (subset == WD_FULL ? 2 : 1); }
 
 wd_status make_geom(const wd_lattice* lat, Geom* g);
@@ -151,7 +157,9 @@ wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, co
 
 // ---- ptconv.hip ----------------------------------------------------------------
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples);
+// FULL float32 spinor <-> 4-channel features; even_only: the spinor is one EVEN half
+// field (odd sites are zero on the way in and dropped on the way out).
 wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, void* spinor, void* feat,
-                                 bool to_features);
+                                 bool to_features, bool even_only = false);
 
 } // namespace wd

@@ -308,7 +308,7 @@ def tune_get(ctx, key):
     return None
 
 
-def solver_params(tol=1e-10, maxiter=10000, sloppy=F32, delta=0.1, pure_sloppy=False):
+def solver_params(tol=1e-10, maxiter=10000, sloppy=F32, delta=-1.0, pure_sloppy=False):
     p = WdSolverParams()
     p.tol = tol
     p.maxiter = maxiter

@@ -274,6 +274,62 @@ def test_wilson_solve_full_system(w, ctx, sloppy):
     assert res <= 1.05 * tol, (res, info.as_dict())
 
 
+@pytest.mark.parametrize("sloppy,delta", [("f32", 0.1), ("f32", 1e-4), ("f16", -1.0), ("bf16", 0.1), ("bf16", -1.0)])
+def test_cg_reliable_update_thresholds(w, ctx, sloppy, delta):
+    """Explicit and default (delta < 0) reliable-update thresholds reach the FP64-checked
+    tolerance; the number of updates falls as delta does."""
+    dims, kappa, tol = (8, 8, 8, 16), 0.1245, 1e-10
+    U, g = gauge(w, ctx, dims, 0.6, 3002, 12)
+    lat = w.lattice(dims, BC)
+    c = source(w, dims, w.EVEN, 32)
+    fb = w.pack(ctx, lat, w.EVEN, w.F64, c)
+    runs = {}
+    for d in (delta, 0.3):
+        fx = w.pack(ctx, lat, w.EVEN, w.F64, np.zeros_like(c))
+        prm = w.solver_params(tol=tol, maxiter=2000, sloppy=w.PREC_BY_NAME[sloppy], delta=d)
+        info = w.WdSolverInfo()
+        w.wd_cg_solve(g.handle, kappa, w.EVEN, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info))
+        x = w.unpack(ctx, lat, w.EVEN, w.F64, fx, c.shape)
+        res = orc.rel_residual(lambda v: orc.mhat_dag_mhat(U, v, kappa, BC), x, c)
+        assert info.status == w.WD_OK and res <= 1.05 * tol, (d, res, info.as_dict())
+        runs[d] = info.reliable_updates
+    assert runs[delta] <= runs[0.3]
+
+
+def test_cg_rejects_bad_delta(w, ctx):
+    dims = (4, 4, 4, 4)
+    U, g = gauge(w, ctx, dims, 0.5, 3003, 12)
+    lat = w.lattice(dims, BC)
+    c = source(w, dims, w.EVEN, 33)
+    fb = w.pack(ctx, lat, w.EVEN, w.F64, c)
+    fx = w.pack(ctx, lat, w.EVEN, w.F64, np.zeros_like(c))
+    lib = w._raw()
+    for d in (1.0, 2.5, float("nan")):
+        prm = w.solver_params(tol=1e-8, maxiter=100, sloppy=w.F32, delta=d)
+        info = w.WdSolverInfo()
+        assert lib.wd_cg_solve(g.handle, 0.12, w.EVEN, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(),
+                               ctypes.byref(info)) == w.WD_EINVAL
+
+
+def test_cg_pure_sloppy_stalls_at_single_precision(w, ctx):
+    """Without reliable updates the FP32 recurrences stop where the iterated residual
+    meets the target; the FP64-checked residual then sits far above it."""
+    dims, kappa, tol = (8, 8, 8, 16), 0.1245, 1e-12
+    U, g = gauge(w, ctx, dims, 0.6, 3004, 12)
+    lat = w.lattice(dims, BC)
+    c = source(w, dims, w.EVEN, 34)
+    fb = w.pack(ctx, lat, w.EVEN, w.F64, c)
+    fx = w.pack(ctx, lat, w.EVEN, w.F64, np.zeros_like(c))
+    prm = w.solver_params(tol=tol, maxiter=3000, sloppy=w.F32, pure_sloppy=True)
+    info = w.WdSolverInfo()
+    w.wd_cg_solve(g.handle, kappa, w.EVEN, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
+                  ok=(w.WD_OK, w.WD_ENOCONV))
+    x = w.unpack(ctx, lat, w.EVEN, w.F64, fx, c.shape)
+    res = orc.rel_residual(lambda v: orc.mhat_dag_mhat(U, v, kappa, BC), x, c)
+    assert info.reliable_updates == 0 and info.status == w.WD_ENOCONV
+    assert 1e-9 < res < 1e-4 and abs(res - info.true_resid) <= 1e-2 * res
+
+
 def test_cg_maxiter_reports_noconv(w, ctx):
     dims, kappa = (4, 6, 2, 10), 0.124
     U, g = gauge(w, ctx, dims, 0.5, 77, 12)
