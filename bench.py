@@ -213,6 +213,7 @@ def learned_extras(w, ctx):
         out["mean_" + k] = {"iters": float(np.mean([r[k]["iters"] for r in rows])),
                             "wall_ms": round(1e3 * float(np.mean([r[k]["wall_s"] for r in rows])), 3)}
     out["learned_speedup_vs_plain_cg"] = round(out["mean_plain_cg_f32"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
+    out["learned_speedup_vs_fgmres_no_net"] = round(out["mean_fgmres_no_net"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
     return out
 
 

@@ -8,7 +8,9 @@ Training data (per gauge field, generated on the fly on the GPU):
 For each psi the pair (M psi, psi) is formed with the library's FP32 Wilson
 operator, and the network N is trained so that N(M psi) ~ psi:
     loss = mean over the batch of ||N(M psi) - psi||^2 / ||psi||^2,
-with Adam on float32 master weights; the kernels may run the weights at 16 bits.
+with Adam on float32 master weights (cosine-decayed learning rate); the kernels
+may run the weights at 16 bits.  The flexible GMRES uses the even-even block of
+N as its preconditioner for the Schur complement Mhat, since (M^-1)_ee = Mhat^-1.
 
 Solve comparison on unseen fields: the plain solver (even-odd CG on
 Mhat^dag Mhat with FP32 storage and FP64 reliable updates), flexible GMRES
@@ -106,10 +108,14 @@ def batch_loss(net, field, x, t, n):
 
 
 def train(net, fields, kappa, pairs_per_field=512, batch=8, epochs=1, lr=2e-3, n_null=16, seed=0, log=None,
-          time_budget_s=None):
-    """Train `net` on the given fields; returns a history dict."""
+          time_budget_s=None, cosine=True):
+    """Train `net` on the given fields; returns a history dict.  cosine: the learning
+    rate decays from lr to 0 over the run as 0.5 (1 + cos(pi step / steps))."""
     gen = torch.Generator().manual_seed(seed)
     opt = torch.optim.Adam(net.parameters(), lr=lr)
+    total_steps = max(1, epochs * max(1, pairs_per_field // batch) * len(fields))
+    sched = torch.optim.lr_scheduler.LambdaLR(
+        opt, (lambda k: 0.5 * (1.0 + np.cos(np.pi * min(k, total_steps) / total_steps))) if cosine else (lambda k: 1.0))
     hist = {"loss": [], "seconds": 0.0, "pairs": 0}
     t0 = time.perf_counter()
     nulls = []
@@ -130,6 +136,7 @@ def train(net, fields, kappa, pairs_per_field=512, batch=8, epochs=1, lr=2e-3, n
                 opt.zero_grad()
                 loss.backward()
                 opt.step()
+                sched.step()
                 hist["loss"].append(loss.item())
                 hist["pairs"] += batch
             if log and s % 8 == 0:
@@ -229,6 +236,7 @@ def main(argv=None):
     ap.add_argument("--wprec", default="bf16")
     ap.add_argument("--restart", type=int, default=16)
     ap.add_argument("--time-budget", type=float, default=None, help="seconds of training at most")
+    ap.add_argument("--no-cosine", action="store_true", help="constant learning rate")
     ap.add_argument("--save", default=None)
     args = ap.parse_args(argv)
     log = lambda m: print("learn: " + m, file=sys.stderr, flush=True)
@@ -239,13 +247,14 @@ def main(argv=None):
     loss0 = evaluate_loss(net, train_f, args.kappa)
     log("initial loss %.4f; training" % loss0)
     hist = train(net, train_f, args.kappa, args.pairs, args.batch, args.epochs, args.lr, args.n_null, log=log,
-                 time_budget_s=args.time_budget)
+                 time_budget_s=args.time_budget, cosine=not args.no_cosine)
     for f in train_f:
         f.close()
     if args.save:
         np.savez(args.save, *[p.detach().cpu().numpy() for p in net.weights], widths=np.array(args.widths))
     test_f = [Field(ctx, args.dims, args.eps, 6001 + i) for i in range(args.test_fields)]
     out = {"dims": args.dims, "eps": args.eps, "kappa": args.kappa, "widths": args.widths, "wprec": args.wprec,
+           "epochs": args.epochs,
            "train": {"pairs": hist["pairs"], "seconds": round(hist["seconds"], 2),
                      "near_null_seconds": round(hist["near_null_seconds"], 2), "loss_initial": loss0,
                      "loss_final_train": float(np.mean(hist["loss"][-8:]))},

@@ -106,3 +106,4 @@ def test_training_lowers_the_loss():
     for f in fields:
         f.close()
     ctx.close()
+
