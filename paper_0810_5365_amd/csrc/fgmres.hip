@@ -18,6 +18,8 @@
 // multi-axpy per pass).  The plain solver is the fallback: a NaN, or a cycle
 // that fails to reduce the true residual tenfold, hands x to the even-odd CG
 // (wd_wilson_solve), which then finishes the solve.
+#include <stdlib.h>
+
 #include <chrono>
 #include <cmath>
 #include <algorithm>
@@ -43,10 +45,15 @@ static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, v
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
     WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true, true));
+    // WD_PTCONV_PARITY_SKIP=0 computes every path and site (same result, for checking)
+    const char* env = getenv("WD_PTCONV_PARITY_SKIP");
+    const bool skip = !(env && atoi(env) == 0);
     void* cur = fa;
     void* nxt = fb;
     for (int l = 0; l < net.nlayers; ++l) {
-        WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1));
+        // the input's odd sites are zero, and only the even output sites are used
+        WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1,
+                          skip && l == 0 ? 1 : -1, skip && l == net.nlayers - 1));
         std::swap(cur, nxt);
     }
     return launch_spinor_features(ctx, G, 1, z, cur, false, true);

@@ -33,6 +33,12 @@ struct PTArgs {
     Geom g;
     int cin;
     long long in_sample, out_sample;   // float2 elements between samples
+    // Matrix-core path only (the vector path computes everything, which gives the same
+    // result): input sites of parity zero_par (0 or 1; -1: none) are known to be zero, so
+    // waves skip the paths that read only them; output sites [0, out_sites) are computed
+    // (2 Vh: both parities; Vh: the even half).
+    int zero_par = -1;
+    int out_sites = 0;
 };
 
 __device__ __forceinline__ size_t fidx(int c, int par, int k, int Vh, uint32_t cb)
@@ -413,19 +419,28 @@ __device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int 
     }
 }
 
+// Each wave stages its operands in its own LDS region, so the lanes of one wave only have
+// to agree with each other: a wavefront-scope fence and wave barrier, no workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int PATH, int R, int CIN>
 __device__ __forceinline__ void mf_path(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4], int lane,
                                         uint16_t* B, const bf16x4& Af, f32x4* acc)
 {
     mf_stage<PATH, R, CIN>(A, in, par, cb, c, lane, B);
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
         const int n = t * 16 + (lane & 15);
         const bf16x4 bf = *(const bf16x4*)&B[n * MF_LD + 4 * (lane >> 4)];
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Af, bf, acc[t], 0, 0, 0);
     }
-    __syncthreads();
+    wave_lds_sync();
 }
 
 template <int R, int CIN, int COUT>
@@ -437,8 +452,9 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     const uint32_t Vh = (uint32_t)A.g.Vh;
     const uint32_t site0 = (blockIdx.x * 4 + wave) * 64;
     const uint32_t idx = site0 + lane;
+    const uint32_t nout = (uint32_t)A.out_sites;
     // lanes past the end stage site 0 (in bounds); their columns are never stored
-    const uint32_t sidx = idx < 2 * Vh ? idx : 0;
+    const uint32_t sidx = idx < nout ? idx : 0;
     const int par = sidx >= Vh ? 1 : 0;
     const uint32_t cb = sidx - (uint32_t)par * Vh;
     const float2* in = A.in + (size_t)blockIdx.y * A.in_sample;
@@ -472,22 +488,31 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     f32x4 acc[12];
 #pragma unroll
     for (int t = 0; t < 12; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    mf_path<0, R, CIN>(A, in, par, cb, c, lane, B, Af[0], acc);
-    mf_path<1, R, CIN>(A, in, par, cb, c, lane, B, Af[1], acc);
-    mf_path<2, R, CIN>(A, in, par, cb, c, lane, B, Af[2], acc);
-    mf_path<3, R, CIN>(A, in, par, cb, c, lane, B, Af[3], acc);
-    mf_path<4, R, CIN>(A, in, par, cb, c, lane, B, Af[4], acc);
-    mf_path<5, R, CIN>(A, in, par, cb, c, lane, B, Af[5], acc);
-    mf_path<6, R, CIN>(A, in, par, cb, c, lane, B, Af[6], acc);
-    mf_path<7, R, CIN>(A, in, par, cb, c, lane, B, Af[7], acc);
-    mf_path<8, R, CIN>(A, in, par, cb, c, lane, B, Af[8], acc);
+    // Parity of the wave's sites, if it is one parity (wave-uniform: from scalars only).
+    // The stay path reads the site's own parity, the hops the other one; a path whose
+    // sources are all known zeros is skipped.
+    const uint32_t last = site0 + 63 < nout ? site0 + 63 : nout - 1;
+    const int wpar0 = site0 >= Vh ? 1 : 0, wpar1 = last >= Vh ? 1 : 0;
+    const bool skip_stay = A.zero_par >= 0 && wpar0 == wpar1 && wpar0 == A.zero_par;
+    const bool skip_hops = A.zero_par >= 0 && wpar0 == wpar1 && 1 - wpar0 == A.zero_par;
+    if (!skip_stay) mf_path<0, R, CIN>(A, in, par, cb, c, lane, B, Af[0], acc);
+    if (!skip_hops) {
+        mf_path<1, R, CIN>(A, in, par, cb, c, lane, B, Af[1], acc);
+        mf_path<2, R, CIN>(A, in, par, cb, c, lane, B, Af[2], acc);
+        mf_path<3, R, CIN>(A, in, par, cb, c, lane, B, Af[3], acc);
+        mf_path<4, R, CIN>(A, in, par, cb, c, lane, B, Af[4], acc);
+        mf_path<5, R, CIN>(A, in, par, cb, c, lane, B, Af[5], acc);
+        mf_path<6, R, CIN>(A, in, par, cb, c, lane, B, Af[6], acc);
+        mf_path<7, R, CIN>(A, in, par, cb, c, lane, B, Af[7], acc);
+        mf_path<8, R, CIN>(A, in, par, cb, c, lane, B, Af[8], acc);
+    }
     const int g = lane >> 4;
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
         const int n = t * 16 + (lane & 15);
         const int k = n >> 6;
         const uint32_t s = site0 + (n & 63);
-        if (s >= 2 * Vh) continue;
+        if (s >= nout) continue;
         const int sp = s >= Vh ? 1 : 0;
         const uint32_t scb = s - (uint32_t)sp * Vh;
         if (2 * g < COUT) out[fidx(2 * g, sp, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
@@ -498,7 +523,7 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
 template <int R>
 static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples)
 {
-    dim3 grid((2 * A.g.Vh + 255) / 256, nsamples), block(256);
+    dim3 grid((A.out_sites + 255) / 256, nsamples), block(256);
     if (cin == 4 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8>), grid, block, 0, ctx->stream, A);
     else if (cin == 8 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8>), grid, block, 0, ctx->stream, A);
     else if (cin == 8 && cout == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4>), grid, block, 0, ctx->stream, A);
@@ -530,7 +555,7 @@ static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples
 }
 
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
-                            int nsamples)
+                            int nsamples, int zero_par, bool even_out)
 {
     const void* links;
     WD_TRY(gauge_links(g, WD_F32, &links));
@@ -543,6 +568,8 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
     A.cin = cin;
     A.in_sample = (long long)cin * 6 * g->geom.Vh;
     A.out_sample = (long long)cout * 6 * g->geom.Vh;
+    A.zero_par = zero_par;
+    A.out_sites = even_out ? g->geom.Vh : 2 * g->geom.Vh;
     const bool r12 = g->recon == 12;
     if (use_mfma(wprec, cin, cout)) return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples) : mfma_r<18>(g->ctx, A, cin, cout, nsamples);
     switch (wprec) {

@@ -156,7 +156,10 @@ wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, co
                      const double* coef, const void* w, double scale, void* out);
 
 // ---- ptconv.hip ----------------------------------------------------------------
-wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples);
+// zero_par >= 0: input sites of that parity are zero (the matrix-core path skips the paths
+// that read only them); even_out: only the even output sites are needed.
+wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples,
+                     int zero_par = -1, bool even_out = false);
 // FULL float32 spinor <-> 4-channel features; even_only: the spinor is one EVEN half
 // field (odd sites are zero on the way in and dropped on the way out).
 wd_status launch_spinor_features(wd_context ctx, const Geom& g, int nsamples, void* spinor, void* feat,

@@ -77,6 +77,33 @@ def test_fgmres_with_network(env, wprec):
     assert res <= 1.05e-10, (res, info.as_dict())
 
 
+def test_fgmres_parity_skips_change_nothing(env, monkeypatch):
+    """The network's first layer skips paths that read the zero odd half of (v_e, 0), the last
+    computes only even sites; with bf16 weights on the matrix cores the skipped terms are exact
+    zeros, so the whole solve is bit-identical to computing every path and site."""
+    import torch
+    from paper_0810_5365_amd import ptconv as pt, learn
+    w, ctx, dims, U, g = env
+    net = learn.load_net(learn.DEFAULT_WEIGHTS, w.BF16)
+    lat = w.lattice(dims, BC)
+    X, Y, Z, T = dims
+    fb = w.pack(ctx, lat, w.FULL, w.F64, ls.gaussian_complex((T, Z, Y, X, 4, 3), 10, ls.STREAM_SPINOR))
+    ws = net.storage()
+    wid = (ctypes.c_int * len(net.widths))(*net.widths)
+    ptrs = (ctypes.c_void_p * len(ws))(*[t.data_ptr() for t in ws])
+    out = []
+    for flag in ("1", "0"):
+        monkeypatch.setenv("WD_PTCONV_PARITY_SKIP", flag)
+        fx = torch.zeros_like(fb)
+        prm = w.solver_params(tol=1e-10, maxiter=500, sloppy=w.F32, delta=1e-4)
+        info = w.WdSolverInfo()
+        w.wd_fgmres_solve(g.handle, 0.1248, ctypes.byref(prm), 16, len(ws), wid, ptrs, net.wprec, fb.data_ptr(),
+                          fx.data_ptr(), ctypes.byref(info))
+        out.append((fx.clone(), info.iters, info.true_resid_M))
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    assert torch.equal(out[0][0], out[1][0])
+
+
 def test_fgmres_falls_back_on_a_broken_network(env):
     import torch
     from paper_0810_5365_amd import ptconv as pt
