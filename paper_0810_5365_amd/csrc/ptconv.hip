@@ -127,7 +127,9 @@ __device__ __forceinline__ void ptconv_dir(const PTArgs& A, const float2* in, in
 template <int R, int COUT, int WP>
 __global__ void __launch_bounds__(256) ptconv_fwd_kernel(PTArgs A)
 {
-    const uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+    // XCD-aware order: each XCD (own L2) walks one contiguous run of sites, so the neighbour
+    // features and links a block reads were mostly fetched into the same L2 by its neighbours
+    const uint32_t idx = xcd_remap(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     const uint32_t Vh = (uint32_t)A.g.Vh;
     if (idx >= 2 * Vh) return;
     const int par = idx >= Vh ? 1 : 0;
@@ -450,13 +452,16 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint16_t* B = lds[wave];
     const uint32_t Vh = (uint32_t)A.g.Vh;
-    const uint32_t site0 = (blockIdx.x * 4 + wave) * 64;
-    const uint32_t idx = site0 + lane;
-    const uint32_t nout = (uint32_t)A.out_sites;
+    // Every wave covers 64 consecutive checkerboard sites of one parity.  With both
+    // parities computed, consecutive waves alternate parity over the same cb range, and
+    // blocks run in XCD-contiguous order: the even and odd sites of one region (which read
+    // each other's features and share their links) fill the same L2.
+    const bool both = A.out_sites > (int)Vh;
+    const uint32_t gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
+    const int par = both ? (int)(gw & 1) : 0;
+    const uint32_t cb0 = (both ? gw >> 1 : gw) * 64;
     // lanes past the end stage site 0 (in bounds); their columns are never stored
-    const uint32_t sidx = idx < nout ? idx : 0;
-    const int par = sidx >= Vh ? 1 : 0;
-    const uint32_t cb = sidx - (uint32_t)par * Vh;
+    const uint32_t cb = cb0 + lane < Vh ? cb0 + lane : 0;
     const float2* in = A.in + (size_t)blockIdx.y * A.in_sample;
     float2* out = A.out + (size_t)blockIdx.y * A.out_sample;
     int c[4];
@@ -488,13 +493,10 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     f32x4 acc[12];
 #pragma unroll
     for (int t = 0; t < 12; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
-    // Parity of the wave's sites, if it is one parity (wave-uniform: from scalars only).
-    // The stay path reads the site's own parity, the hops the other one; a path whose
-    // sources are all known zeros is skipped.
-    const uint32_t last = site0 + 63 < nout ? site0 + 63 : nout - 1;
-    const int wpar0 = site0 >= Vh ? 1 : 0, wpar1 = last >= Vh ? 1 : 0;
-    const bool skip_stay = A.zero_par >= 0 && wpar0 == wpar1 && wpar0 == A.zero_par;
-    const bool skip_hops = A.zero_par >= 0 && wpar0 == wpar1 && 1 - wpar0 == A.zero_par;
+    // The stay path reads the wave's own parity, the hops the other one; a path whose
+    // sources are all known zeros is skipped (par is wave-uniform).
+    const bool skip_stay = A.zero_par >= 0 && par == A.zero_par;
+    const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
     if (!skip_stay) mf_path<0, R, CIN>(A, in, par, cb, c, lane, B, Af[0], acc);
     if (!skip_hops) {
         mf_path<1, R, CIN>(A, in, par, cb, c, lane, B, Af[1], acc);
@@ -511,19 +513,18 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     for (int t = 0; t < 12; ++t) {
         const int n = t * 16 + (lane & 15);
         const int k = n >> 6;
-        const uint32_t s = site0 + (n & 63);
-        if (s >= nout) continue;
-        const int sp = s >= Vh ? 1 : 0;
-        const uint32_t scb = s - (uint32_t)sp * Vh;
-        if (2 * g < COUT) out[fidx(2 * g, sp, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
-        if (2 * g + 1 < COUT) out[fidx(2 * g + 1, sp, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
+        const uint32_t scb = cb0 + (n & 63);
+        if (scb >= Vh) continue;
+        if (2 * g < COUT) out[fidx(2 * g, par, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
+        if (2 * g + 1 < COUT) out[fidx(2 * g + 1, par, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
     }
 }
 
 template <int R>
 static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples)
 {
-    dim3 grid((A.out_sites + 255) / 256, nsamples), block(256);
+    const int waves = (A.out_sites > A.g.Vh ? 2 : 1) * ((A.g.Vh + 63) / 64);
+    dim3 grid((waves + 3) / 4, nsamples), block(256);
     if (cin == 4 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8>), grid, block, 0, ctx->stream, A);
     else if (cin == 8 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8>), grid, block, 0, ctx->stream, A);
     else if (cin == 8 && cout == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4>), grid, block, 0, ctx->stream, A);
