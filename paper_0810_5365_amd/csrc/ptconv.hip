@@ -374,53 +374,6 @@ __device__ __forceinline__ uint32_t cvt_bf16x2(float a, float b)
 }
 constexpr int MF_LD = 20;   // bf16 per staged column: 16 K values + 4 of padding (40 B, conflict-free reads)
 
-template <int PATH, int R, int CIN>
-__device__ __forceinline__ void mf_stage(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
-                                         int lane, uint16_t* B)
-{
-    const int Vh = A.g.Vh;
-    float u[18];
-    uint32_t src = cb;
-    int spar = par;
-    bool dag = false;
-    if constexpr (PATH > 0) {
-        constexpr int MU = (PATH - 1) & 3;
-        constexpr bool FWD = PATH <= 4;
-        const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
-        const int lpar = FWD ? par : 1 - par;
-        LinkIO<P_F32, R, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps, A.g.ps,
-                                      FWD ? cb : nb, u);
-        // boundary sign folded into the (reconstructed) link: 18 products instead of 6 C_in
-        const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
-#pragma unroll
-        for (int i = 0; i < 18; ++i) u[i] *= sign;
-        src = nb;
-        spar = 1 - par;
-        dag = !FWD;
-    }
-    // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
-    const float2* site = in + (size_t)spar * 3 * Vh + src;
-#pragma unroll
-    for (int b = 0; b < CIN; ++b) {
-        float v[6], t[6];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const float2 q = site[(size_t)(b * 6 + k) * Vh];
-            v[2 * k] = q.x;
-            v[2 * k + 1] = q.y;
-        }
-        if constexpr (PATH > 0) {
-            mat_vec(u, v, t, dag);
-        } else {
-#pragma unroll
-            for (int i = 0; i < 6; ++i) t[i] = v[i];
-        }
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(t[2 * k], t[2 * k + 1]);
-    }
-}
-
 // Each wave stages its operands in its own LDS region, so the lanes of one wave only have
 // to agree with each other: a wavefront-scope fence and wave barrier, no workgroup barrier.
 __device__ __forceinline__ void wave_lds_sync()
@@ -430,11 +383,84 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// One path in two halves so that the loads of path p + 1 are in flight while path p is
+// transported, staged and multiplied (the layer is latency-bound on small lattices:
+// one wave per 64 sites walks all nine paths).
+template <int R, int CIN> struct MfRaw {
+    float4 l[R == 12 ? 3 : 4];   // link planes as loaded (row 2 rebuilt later for 12 reals)
+    float2 l18;                  // last two reals of an 18-real link
+    float2 v[CIN][3];            // neighbour features, channel b, colour k
+};
+
 template <int PATH, int R, int CIN>
-__device__ __forceinline__ void mf_path(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4], int lane,
-                                        uint16_t* B, const bf16x4& Af, f32x4* acc)
+__device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
+                                        MfRaw<R, CIN>& x)
 {
-    mf_stage<PATH, R, CIN>(A, in, par, cb, c, lane, B);
+    const int Vh = A.g.Vh;
+    uint32_t src = cb;
+    int spar = par;
+    if constexpr (PATH > 0) {
+        constexpr int MU = (PATH - 1) & 3;
+        constexpr bool FWD = PATH <= 4;
+        const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
+        const int lpar = FWD ? par : 1 - par;
+        const float4* grp =
+            (const float4*)(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps) + (FWD ? cb : nb);
+#pragma unroll
+        for (int k = 0; k < (R == 12 ? 3 : 4); ++k) x.l[k] = grp[(size_t)k * A.g.ps];
+        if constexpr (R == 18) x.l18 = ((const float2*)(grp - (FWD ? cb : nb) + (size_t)4 * A.g.ps))[FWD ? cb : nb];
+        src = nb;
+        spar = 1 - par;
+    }
+    // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
+    const float2* site = in + (size_t)spar * 3 * Vh + src;
+#pragma unroll
+    for (int b = 0; b < CIN; ++b)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x.v[b][k] = site[(size_t)(b * 6 + k) * Vh];
+}
+
+template <int PATH, int R, int CIN>
+__device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int lane, uint16_t* B,
+                                           const MfRaw<R, CIN>& x, const bf16x4& Af, f32x4* acc)
+{
+    float u[18];
+    if constexpr (PATH > 0) {
+        constexpr int MU = (PATH - 1) & 3;
+        constexpr bool FWD = PATH <= 4;
+#pragma unroll
+        for (int k = 0; k < (R == 12 ? 3 : 4); ++k) {
+            u[4 * k] = x.l[k].x; u[4 * k + 1] = x.l[k].y; u[4 * k + 2] = x.l[k].z; u[4 * k + 3] = x.l[k].w;
+        }
+        if constexpr (R == 18) {
+            u[16] = x.l18.x;
+            u[17] = x.l18.y;
+        } else {
+            reconstruct_row2(u);
+        }
+        // boundary sign folded into the (reconstructed) link: 18 products instead of 6 C_in
+        const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
+#pragma unroll
+        for (int i = 0; i < 18; ++i) u[i] *= sign;
+    }
+#pragma unroll
+    for (int b = 0; b < CIN; ++b) {
+        float v[6], t[6];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            v[2 * k] = x.v[b][k].x;
+            v[2 * k + 1] = x.v[b][k].y;
+        }
+        if constexpr (PATH > 0) {
+            mat_vec(u, v, t, PATH > 4);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 6; ++i) t[i] = v[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(t[2 * k], t[2 * k + 1]);
+    }
     wave_lds_sync();
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
@@ -445,8 +471,19 @@ __device__ __forceinline__ void mf_path(const PTArgs& A, const float2* in, int p
     wave_lds_sync();
 }
 
+// paths P..LAST, each one's loads issued before the previous one's arithmetic
+template <int P, int LAST, int R, int CIN>
+__device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
+                                        int lane, uint16_t* B, const bf16x4* Af, f32x4* acc, MfRaw<R, CIN>& cur,
+                                        MfRaw<R, CIN>& nxt)
+{
+    if constexpr (P < LAST) mf_load<P + 1, R, CIN>(A, in, par, cb, c, nxt);
+    mf_compute<P, R, CIN>(A, c, lane, B, cur, Af[P], acc);
+    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
+}
+
 template <int R, int CIN, int COUT>
-__global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
+__global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -497,16 +534,16 @@ __global__ void __launch_bounds__(256) ptconv_mfma_kernel(PTArgs A)
     // sources are all known zeros is skipped (par is wave-uniform).
     const bool skip_stay = A.zero_par >= 0 && par == A.zero_par;
     const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
-    if (!skip_stay) mf_path<0, R, CIN>(A, in, par, cb, c, lane, B, Af[0], acc);
-    if (!skip_hops) {
-        mf_path<1, R, CIN>(A, in, par, cb, c, lane, B, Af[1], acc);
-        mf_path<2, R, CIN>(A, in, par, cb, c, lane, B, Af[2], acc);
-        mf_path<3, R, CIN>(A, in, par, cb, c, lane, B, Af[3], acc);
-        mf_path<4, R, CIN>(A, in, par, cb, c, lane, B, Af[4], acc);
-        mf_path<5, R, CIN>(A, in, par, cb, c, lane, B, Af[5], acc);
-        mf_path<6, R, CIN>(A, in, par, cb, c, lane, B, Af[6], acc);
-        mf_path<7, R, CIN>(A, in, par, cb, c, lane, B, Af[7], acc);
-        mf_path<8, R, CIN>(A, in, par, cb, c, lane, B, Af[8], acc);
+    MfRaw<R, CIN> ra, rb;
+    if (skip_hops) {
+        mf_load<0, R, CIN>(A, in, par, cb, c, ra);
+        mf_compute<0, R, CIN>(A, c, lane, B, ra, Af[0], acc);
+    } else if (skip_stay) {
+        mf_load<1, R, CIN>(A, in, par, cb, c, ra);
+        mf_pipe<1, 8, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+    } else {
+        mf_load<0, R, CIN>(A, in, par, cb, c, ra);
+        mf_pipe<0, 8, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     }
     const int g = lane >> 4;
 #pragma unroll
