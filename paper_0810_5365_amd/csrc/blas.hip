@@ -78,12 +78,16 @@ static int red_blocks(long long nsites)
     return (int)(b < RED_MAXBLOCKS ? (b < 1 ? 1 : b) : RED_MAXBLOCKS);
 }
 
-static wd_status finish(wd_context ctx, int nblk, int n, bool fetch)
+// Values land in dres[slot ..] and its host copy hres[slot ..] (mapped: written by the
+// kernel; else copied behind it on the stream).
+static wd_status finish(wd_context ctx, int nblk, int n, bool fetch, int slot = 0)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, ctx->dres,
-                       ctx->hres_dev);
+    hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, ctx->dres + slot,
+                       ctx->hres_dev ? ctx->hres_dev + slot : nullptr);
     WD_LAUNCHED();
-    if (fetch) return fetch_results(ctx, n);
+    if (!ctx->hres_dev && slot != 0)
+        WD_HIP(hipMemcpyAsync(ctx->hres + slot, ctx->dres + slot, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    if (fetch) return fetch_results(ctx, slot == 0 ? n : 0);
     return WD_OK;
 }
 
@@ -425,47 +429,59 @@ wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nh, int prec, double 
 }
 
 // ---- block Gram-Schmidt helpers (flexible GMRES) ---------------------------------------
-// <V_i, w> for i < k, and (with_norm) ||w||^2 as value k: one launch, one fetch.
+// <V_i, w> for i < k, and (with_norm) ||w||^2 as value k.  Vectors go in groups of four:
+// w is read once per group, so a pass reads k + ceil((k + 1) / 4) fields instead of 2 (k + 1).
+constexpr int MDOT_GROUP = 4;
+
 template <int P>
 __global__ void __launch_bounds__(RED_BLOCK) mdot_kernel(SiteRange Vs, size_t vstride, int k, int with_norm, SiteRange W,
                                                          long long nsites, double* partials)
 {
     const int n = k + (with_norm ? 1 : 0);
-    for (int i = 0; i < n; ++i) {
-        double acc[2] = {0.0, 0.0};
+    for (int i0 = 0; i0 < n; i0 += MDOT_GROUP) {
+        double acc[2 * MDOT_GROUP];
+#pragma unroll
+        for (int q = 0; q < 2 * MDOT_GROUP; ++q) acc[q] = 0.0;
         for (long long s = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; s < nsites; s += (long long)gridDim.x * RED_BLOCK) {
             const long long h = s / W.Vh;
             const uint32_t cb = (uint32_t)(s - h * W.Vh);
-            typename RealOf<P>::T a[24], b[24];
+            typename RealOf<P>::T b[24];
             SpinorIO<P>::load(W.half(h), W.ps, cb, b);
-            if (i < k) SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, a);
-            else {
 #pragma unroll
-                for (int q = 0; q < 24; ++q) a[q] = b[q];
-            }
+            for (int u = 0; u < MDOT_GROUP; ++u) {
+                const int i = i0 + u;
+                if (i >= n) break;
+                typename RealOf<P>::T a[24];
+                if (i < k) SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, a);
+                else {
 #pragma unroll
-            for (int q = 0; q < 12; ++q) {
-                const double ar = a[2 * q], ai = a[2 * q + 1], br = b[2 * q], bi = b[2 * q + 1];
-                acc[0] += ar * br + ai * bi;
-                acc[1] += ar * bi - ai * br;
+                    for (int q = 0; q < 24; ++q) a[q] = b[q];
+                }
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const double ar = a[2 * q], ai = a[2 * q + 1], br = b[2 * q], bi = b[2 * q + 1];
+                    acc[2 * u] += ar * br + ai * bi;
+                    acc[2 * u + 1] += ar * bi - ai * br;
+                }
             }
         }
-        block_reduce<2>(acc, partials + (size_t)2 * i * gridDim.x);
+        block_reduce<2 * MDOT_GROUP>(acc, partials + (size_t)2 * i0 * gridDim.x);
         __syncthreads();
     }
 }
 
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
-                    const void* w, bool with_norm, bool fetch)
+                    const void* w, bool with_norm, bool fetch, int slot)
 {
     const int n = k + (with_norm ? 1 : 0);
-    if (k < 0 || n < 1 || 2 * n > 256) {
-        set_error("mdot: k = %d out of range", k);
+    if (k < 0 || n < 1 || slot < 0 || slot + 2 * n > 256) {
+        set_error("mdot: k = %d (slot %d) out of range", k, slot);
         return WD_EINVAL;
     }
     const long long ns = (long long)nh * g.Vh;
     const int nblk = red_blocks(ns);
-    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2 * n));
+    const int ngrp = (n + MDOT_GROUP - 1) / MDOT_GROUP;
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 2 * MDOT_GROUP * ngrp));
     SiteRange Vs{(const char*)V, g.Vh, g.ps, half_bytes(g, prec)}, W{(const char*)w, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
     case WD_F64: hipLaunchKernelGGL(mdot_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k, (int)with_norm, W, ns, ctx->partials); break;
@@ -473,17 +489,18 @@ wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nh, int prec, const vo
     default: set_error("mdot: precision %d not supported", prec); return WD_EUNSUPPORTED;
     }
     WD_LAUNCHED();
-    return finish(ctx, nblk, 2 * n, fetch);
+    return finish(ctx, nblk, 2 * n, fetch, slot);
 }
 
 struct MaxpyCoef {
     float c[2 * WD_MAXPY];
 };
 
-// out = scale * (w + sum_i c_i V_i); out may be w
+// out = scale * (w + sum_i c_i V_i); out may be w.  With dcoef non-null the coefficients are
+// c_i = dsign * (dcoef[2i], dcoef[2i + 1]), read from device memory (a previous reduction).
 template <int P>
-__global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef cf, float scale, SiteRange W, SiteRange O,
-                             long long n)
+__global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef cf, const double* dcoef, float dsign,
+                             float scale, SiteRange W, SiteRange O, long long n)
 {
     WD_SITE_LOOP(n, W.Vh)
     using T = typename RealOf<P>::T;
@@ -492,7 +509,8 @@ __global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef c
     for (int i = 0; i < nvec; ++i) {
         T v[24];
         SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, v);
-        const T cr = (T)cf.c[2 * i], ci = (T)cf.c[2 * i + 1];
+        const T cr = dcoef ? (T)(dsign * (float)dcoef[2 * i]) : (T)cf.c[2 * i];
+        const T ci = dcoef ? (T)(dsign * (float)dcoef[2 * i + 1]) : (T)cf.c[2 * i + 1];
 #pragma unroll
         for (int q = 0; q < 12; ++q) {
             w[2 * q] += cr * v[2 * q] - ci * v[2 * q + 1];
@@ -504,24 +522,40 @@ __global__ void maxpy_kernel(SiteRange Vs, size_t vstride, int nvec, MaxpyCoef c
     SpinorIO<P>::store((char*)O.half(h), W.ps, cb, w);
 }
 
-wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
-                     const double* coef, const void* w, double scale, void* out)
+static wd_status maxpy_any(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
+                           const double* coef, const double* dcoef, float dsign, const void* w, double scale, void* out)
 {
     if (k < 0 || k > WD_MAXPY) {
         set_error("maxpy: k = %d out of range", k);
         return WD_EINVAL;
     }
     MaxpyCoef cf;
-    for (int i = 0; i < 2 * k; ++i) cf.c[i] = (float)coef[i];
+    for (int i = 0; i < 2 * k; ++i) cf.c[i] = coef ? (float)coef[i] : 0.f;
     const long long n = (long long)nh * g.Vh;
     SiteRange Vs{(const char*)V, g.Vh, g.ps, half_bytes(g, prec)}, W{(const char*)w, g.Vh, g.ps, half_bytes(g, prec)},
         O{(const char*)out, g.Vh, g.ps, half_bytes(g, prec)};
     switch (prec) {
-    case WD_F32: hipLaunchKernelGGL(maxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, Vs, vstride, k, cf, (float)scale, W, O, n); break;
+    case WD_F32: hipLaunchKernelGGL(maxpy_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, Vs, vstride, k, cf, dcoef, dsign, (float)scale, W, O, n); break;
     default: set_error("maxpy: precision %d not supported (F32 only)", prec); return WD_EUNSUPPORTED;
     }
     WD_LAUNCHED();
     return WD_OK;
+}
+
+wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
+                     const double* coef, const void* w, double scale, void* out)
+{
+    return maxpy_any(ctx, g, nh, prec, V, vstride, k, coef, nullptr, 0.f, w, scale, out);
+}
+
+wd_status blas_maxpy_dev(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
+                         int slot, float sign, const void* w, double scale, void* out)
+{
+    if (slot < 0 || slot + 2 * k > 256) {
+        set_error("maxpy: coefficient slot %d out of range", slot);
+        return WD_EINVAL;
+    }
+    return maxpy_any(ctx, g, nh, prec, V, vstride, k, nullptr, ctx->dres + slot, sign, w, scale, out);
 }
 
 // ---- STREAM-style copy: the achievable HBM ceiling and the reference for

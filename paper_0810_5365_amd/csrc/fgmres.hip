@@ -13,9 +13,9 @@
 // params->delta; then x_e += e_e, x_o += r_o + kappa D_oe e_e in float64 (the
 // odd rows of the update are exact, the even rows leave rhat_e - Mhat e_e),
 // and r is recomputed in float64, which decides convergence.
-// Orthogonalisation is classical Gram-Schmidt with a second pass when the
-// first removed most of the vector (one fused multi-dot and one fused
-// multi-axpy per pass).  The plain solver is the fallback: a NaN, or a cycle
+// Orthogonalisation is classical Gram-Schmidt applied twice (one fused
+// multi-dot and one fused multi-axpy per pass; the first pass's coefficients
+// never leave the device, so each iteration waits for the host once).  The plain solver is the fallback: a NaN, or a cycle
 // that fails to reduce the true residual tenfold, hands x to the even-odd CG
 // (wd_wilson_solve), which then finishes the solve.
 #include <stdlib.h>
@@ -138,33 +138,25 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
             WD_TRY(op_M(g, kappa, WD_EVEN, 0, WD_F32, 1, net ? Zi(j) : Vi(j), wv));
             info->operator_applies++;
             info->iters++;
-            // classical Gram-Schmidt with the norm in the same reduction; a second pass only when
-            // the projection removed most of w (Daniel-Gragg-Kaufman-Stewart criterion)
+            // classical Gram-Schmidt applied twice ("twice is enough"): the first pass keeps its
+            // coefficients on the device and feeds the first multi-axpy directly; only the second
+            // pass (with ||w||^2 in the same reduction) waits for the host
+            constexpr int SLOT_H1 = 128;
+            WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, false, false, SLOT_H1));
+            WD_TRY(blas_maxpy_dev(ctx, G, nh, WD_F32, V, v32, j + 1, SLOT_H1, -1.0f, wv, 1.0, wv));
             WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
-            double w2 = ctx->hres[2 * (j + 1)], h2 = 0.0;
+            const double w2 = ctx->hres[2 * (j + 1)];
+            double h2 = 0.0;
             std::vector<double> coef(2 * (j + 1));
             for (int i = 0; i <= j; ++i) {
+                const cd h1((double)(float)ctx->hres[SLOT_H1 + 2 * i], (double)(float)ctx->hres[SLOT_H1 + 2 * i + 1]);
                 const cd h(ctx->hres[2 * i], ctx->hres[2 * i + 1]);
-                H[i][j] = h;
+                H[i][j] = h1 + h;
                 h2 += std::norm(h);
                 coef[2 * i] = -h.real();
                 coef[2 * i + 1] = -h.imag();
             }
-            double hn2 = w2 - h2;
-            if (!(hn2 > 0.5 * w2)) {
-                WD_TRY(blas_maxpy(ctx, G, nh, WD_F32, V, v32, j + 1, coef.data(), wv, 1.0, wv));
-                WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
-                w2 = ctx->hres[2 * (j + 1)];
-                h2 = 0.0;
-                for (int i = 0; i <= j; ++i) {
-                    const cd h(ctx->hres[2 * i], ctx->hres[2 * i + 1]);
-                    H[i][j] += h;
-                    h2 += std::norm(h);
-                    coef[2 * i] = -h.real();
-                    coef[2 * i + 1] = -h.imag();
-                }
-                hn2 = w2 - h2;
-            }
+            const double hn2 = w2 - h2;
             const double hn = std::sqrt(hn2 > 0.0 ? hn2 : 0.0);
             if (!std::isfinite(hn) || !std::isfinite(w2)) {
                 bad = true;

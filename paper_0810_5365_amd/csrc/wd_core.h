@@ -146,14 +146,17 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
-// h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[2i], dres[2i + 1];
-// with_norm adds ||w||^2 in dres[2k]
+// h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[slot + 2i],
+// dres[slot + 2i + 1] (and hres); with_norm adds ||w||^2 in dres[slot + 2k]
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
-                    const void* w, bool with_norm, bool fetch);
+                    const void* w, bool with_norm, bool fetch, int slot = 0);
 // out = scale (w + sum_i c_i V_i), complex c_i = (coef[2i], coef[2i + 1]), i < k <= WD_MAXPY; out may be w
 constexpr int WD_MAXPY = 64;
 wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
                      const double* coef, const void* w, double scale, void* out);
+// the same with c_i = sign (dres[slot + 2i], dres[slot + 2i + 1]) read on the device (no host round trip)
+wd_status blas_maxpy_dev(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
+                         int slot, float sign, const void* w, double scale, void* out);
 
 // ---- ptconv.hip ----------------------------------------------------------------
 // zero_par >= 0: input sites of that parity are zero (the matrix-core path skips the paths
