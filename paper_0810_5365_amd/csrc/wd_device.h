@@ -133,6 +133,13 @@ template <int P> __device__ __forceinline__ uint32_t pack2(float a, float b)
 {
     return f2h<P>(a) | (f2h<P>(b) << 16);
 }
+// bf16 pairs: gfx950 converts two floats with round-to-nearest-even in one instruction
+typedef __bf16 wd_bf16x2 __attribute__((ext_vector_type(2)));
+typedef float wd_f32x2 __attribute__((ext_vector_type(2)));
+template <> __device__ __forceinline__ uint32_t pack2<P_BF16>(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(wd_f32x2{a, b}, wd_bf16x2));
+}
 
 // ---------------------------------------------------------------------------
 // Plane stride.  On a lattice of 2^k sites every plane of a packed field
@@ -279,8 +286,9 @@ template <typename T> __device__ __forceinline__ void reconstruct_row2(T* u)
         const int p = (j + 1) % 3, q = (j + 2) % 3;
         const T ar = u[2 * p], ai = u[2 * p + 1], br = u[6 + 2 * q], bi = u[6 + 2 * q + 1];
         const T cr = u[2 * q], ci = u[2 * q + 1], dr = u[6 + 2 * p], di = u[6 + 2 * p + 1];
-        const T re = (ar * br - ai * bi) - (cr * dr - ci * di);
-        const T im = (ar * bi + ai * br) - (cr * di + ci * dr);
+        // (a b - c d) as chains of fused multiply-adds
+        const T re = fma(ar, br, fma(-ai, bi, fma(-cr, dr, ci * di)));
+        const T im = fma(ar, bi, fma(ai, br, fma(-cr, di, -(ci * dr))));
         u[12 + 2 * j] = re;
         u[12 + 2 * j + 1] = -im;
     }
@@ -423,8 +431,10 @@ template <bool DAG, typename T> __device__ __forceinline__ void su3_mul(const T*
                 const int e = DAG ? (3 * b + a) : (3 * a + b);
                 const T ur = u[2 * e], ui = DAG ? -u[2 * e + 1] : u[2 * e + 1];
                 const T hr = h[6 * s + 2 * b], hi = h[6 * s + 2 * b + 1];
-                re += ur * hr - ui * hi;
-                im += ur * hi + ui * hr;
+                re = fma(ur, hr, re);
+                re = fma(-ui, hi, re);
+                im = fma(ur, hi, im);
+                im = fma(ui, hr, im);
             }
             w[6 * s + 2 * a] = re;
             w[6 * s + 2 * a + 1] = im;
