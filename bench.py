@@ -122,9 +122,16 @@ def extras(w, ctx, stream, torch, ls):
         hb = w.spinor_bytes(lat, w.EVEN, prec)
         us1 = timed(lambda: [w.wd_dslash(g.handle, w.EVEN, 0, prec, 1, fin.data_ptr() + r * hb, fout.data_ptr() + r * hb)
                              for r in range(nrhs)], 10)
-        out["multi_rhs_16c32_%s" % name] = {
-            "nrhs": nrhs, "us_per_call": round(us, 2), "gflops": round(nrhs * Vh * FLOPS_DSLASH / us / 1e3, 1),
-            "us_one_rhs_per_launch": round(us1, 2), "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, nrhs, 0, 0))}
+        rec = {"nrhs": nrhs, "us_per_call": round(us, 2), "gflops": round(nrhs * Vh * FLOPS_DSLASH / us / 1e3, 1),
+               "us_one_rhs_per_launch": round(us1, 2), "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, nrhs, 0, 0))}
+        if prec != w.F32:
+            # the colour multiply of 16 rhs on the matrix cores against the per-rhs kernel
+            for flag, key in (("1", "us_matrix_core_path"), ("0", "us_per_rhs_path")):
+                os.environ["WD_DSLASH_MFMA"] = flag
+                rec[key] = round(timed(lambda: w.wd_dslash(g.handle, w.EVEN, 0, prec, nrhs, fin.data_ptr(),
+                                                           fout.data_ptr()), 50), 2)
+            del os.environ["WD_DSLASH_MFMA"]
+        out["multi_rhs_16c32_%s" % name] = rec
     g.close()
 
     specs = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 32)]

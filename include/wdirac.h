@@ -298,7 +298,9 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
  * prec and nrhs right-hand sides (workgroup size 64..256, XCD-aware block
  * remap, non-temporal link loads, software-pipelined directions, a z-blocked
  * site traversal of depth zb dividing Z and, for nrhs > 1, right-hand sides
- * interleaved with the site tiles), for both
+ * interleaved with the site tiles; for 16-bit storage with 12-real links and a
+ * multiple of 16 rhs also the kernel that runs the colour multiply of 16 rhs on
+ * the matrix cores), for both
  * dagger settings with and without the fused a x + b D in, and keep the
  * fastest in the context's tuning table.  If cache_path is not NULL the file
  * is read first and the whole table written back after.  Synchronous; uses
@@ -310,6 +312,10 @@ wd_status wd_tune_load(wd_context ctx, const char* path);
 /* Look up one tuning entry by key; fills out6 = {block, remap, nt, pf,
  * rhs_inner, zb} and returns 1, or returns 0 if the key is absent. */
 int wd_tune_get(wd_context ctx, const char* key, int* out6);
+/* The same with up to n values {block, remap, nt, pf, rhs_inner, zb, mf}, mf = 1
+ * when the dslash runs its colour multiply on the matrix cores (16-bit storage,
+ * 12-real links, a multiple of 16 rhs); returns 1, or 0 if the key is absent. */
+int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n);
 
 #ifdef __cplusplus
 }

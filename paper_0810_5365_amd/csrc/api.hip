@@ -102,9 +102,16 @@ wd_status ensure_reduction(wd_context ctx, size_t n)
 
 TuneParam tune_lookup(wd_context ctx, const std::string& key)
 {
+    // WD_DSLASH_MFMA forces the matrix-core multi-rhs path on (1) or off (0), tuned or not
+    const char* mf = getenv("WD_DSLASH_MFMA");
     auto it = ctx->tune.find(key);
-    if (it != ctx->tune.end()) return it->second;
+    if (it != ctx->tune.end()) {
+        TuneParam tp = it->second;
+        if (mf) tp.mf = atoi(mf);
+        return tp;
+    }
     TuneParam tp;
+    if (mf) tp.mf = atoi(mf);
     if (const char* e = getenv("WD_DSLASH_BLOCK")) tp.block = atoi(e);
     if (const char* e = getenv("WD_DSLASH_REMAP")) tp.remap = atoi(e);
     if (const char* e = getenv("WD_DSLASH_NT")) tp.nt = atoi(e);

@@ -53,6 +53,7 @@ static wd_status dispatch_pr(wd_context ctx, const DslashArgs& A, const DslashCa
 
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp)
 {
+    if (tp.mf && mrhs_eligible(c)) return launch_dslash_mrhs(ctx, g, c);
     if (tp.block <= 0 || tp.block > 256 || tp.block % 64) {
         set_error("dslash: workgroup size %d not in {64, 128, 192, 256}", tp.block);
         return WD_EINVAL;

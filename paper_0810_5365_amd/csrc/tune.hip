@@ -49,9 +49,9 @@ wd_status tune_save(wd_context ctx, const char* path)
     fprintf(f, "{\"arch\": \"gfx950\", \"entries\": [\n");
     size_t i = 0;
     for (auto& kv : ctx->tune) {
-        fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d, \"ri\": %d, \"zb\": %d}%s\n",
+        fprintf(f, "  {\"key\": \"%s\", \"block\": %d, \"remap\": %d, \"nt\": %d, \"pf\": %d, \"ri\": %d, \"zb\": %d, \"mf\": %d}%s\n",
                 kv.first.c_str(), kv.second.block, kv.second.remap, kv.second.nt, kv.second.pf, kv.second.rhs_inner,
-                kv.second.zb, ++i < ctx->tune.size() ? "," : "");
+                kv.second.zb, kv.second.mf, ++i < ctx->tune.size() ? "," : "");
     }
     fprintf(f, "]}\n");
     fclose(f);
@@ -74,6 +74,8 @@ wd_status tune_load(wd_context ctx, const char* path)
             if (ri) tp.rhs_inner = atoi(ri + 6);
             const char* zb = strstr(p, "\"zb\": ");
             if (zb) tp.zb = atoi(zb + 6);
+            const char* mf = strstr(p, "\"mf\": ");
+            if (mf) tp.mf = atoi(mf + 6);
             if (tp.block >= 64 && tp.block <= 256 && tp.block % 64 == 0) ctx->tune[key] = tp;
         }
     }
@@ -139,6 +141,16 @@ wd_status autotune_dslash(wd_gauge g, int prec, int nrhs, int* ntuned)
                                 best = tp;
                             }
                         }
+            if (mrhs_eligible(c)) {   // the matrix-core path has no launch-shape parameters
+                TuneParam tp;
+                tp.mf = 1;
+                float us;
+                WD_TRY(time_launch(ctx, G, c, tp, reps, &us));
+                if (us < best_us) {
+                    best_us = us;
+                    best = tp;
+                }
+            }
             ctx->tune[dslash_key(G, prec, g->recon, nrhs, dagger, xpay)] = best;
             ++*ntuned;
         }
@@ -184,6 +196,17 @@ wd_status wd_tune_load(wd_context ctx, const char* path)
         return WD_EINVAL;
     }
     return tune_load(ctx, path);
+}
+
+int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n)
+{
+    if (!ctx || !key || !out || n < 0) return 0;
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) return 0;
+    const TuneParam& tp = it->second;
+    const int v[7] = {tp.block, tp.remap, tp.nt, tp.pf, tp.rhs_inner, tp.zb, tp.mf};
+    for (int i = 0; i < n && i < 7; ++i) out[i] = v[i];
+    return 1;
 }
 
 int wd_tune_get(wd_context ctx, const char* key, int* out6)

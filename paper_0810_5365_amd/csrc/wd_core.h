@@ -49,6 +49,7 @@ struct TuneParam {
     int pf = 1;   // software-pipelined directions
     int rhs_inner = 1;   // several rhs: interleave them with the site tiles
     int zb = 0;          // z-blocked site traversal depth (0: natural order)
+    int mf = 0;          // 16-bit, 12-real, 16k rhs: colour multiply on the matrix cores
 };
 
 inline bool valid_prec(int p) { return p >= WD_F64 && p <= WD_BF16; }
@@ -119,6 +120,9 @@ struct DslashCall {
 };
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
+// ---- dslash_mrhs.hip: 16 rhs per wave with the colour multiply on the matrix cores ----
+bool mrhs_eligible(const DslashCall& c);
+wd_status launch_dslash_mrhs(wd_context ctx, const Geom& g, const DslashCall& c);
 
 // ---- pack.hip ----------------------------------------------------------------
 wd_status launch_pack_gauge(wd_context ctx, const Geom& g, int prec, int recon, const double* canon, void* out);

@@ -104,6 +104,7 @@ _PROTOS = {
     "wd_tune_save": ("status", [_V, ctypes.c_char_p]),
     "wd_tune_load": ("status", [_V, ctypes.c_char_p]),
     "wd_tune_get": (_I, [_V, ctypes.c_char_p, _P(_I)]),
+    "wd_tune_get_n": (_I, [_V, ctypes.c_char_p, _P(_I), _I]),
 }
 
 _lib = None
@@ -302,9 +303,10 @@ def dslash_key(dims, prec, recon, nrhs, dagger, xpay):
 
 
 def tune_get(ctx, key):
-    out = (ctypes.c_int * 6)()
-    if wd_tune_get(ctx.handle, key.encode(), out):
-        return {"block": out[0], "remap": out[1], "nt": out[2], "pf": out[3], "rhs_inner": out[4], "zb": out[5]}
+    out = (ctypes.c_int * 7)()
+    if wd_tune_get_n(ctx.handle, key.encode(), out, 7):
+        return {"block": out[0], "remap": out[1], "nt": out[2], "pf": out[3], "rhs_inner": out[4], "zb": out[5],
+                "mfma": out[6]}
     return None
 
 
