@@ -49,19 +49,65 @@ __device__ __forceinline__ void mr_wave_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 16-bit spinor of one site in code units (no scale) and its scale
-template <int P>
-__device__ __forceinline__ float mr_load_codes(const char* base, int ps, uint32_t cb, float* v)
+// Raw loads of one direction: two neighbour spinors (codes and scales) and, in lanes
+// 0..7, the link.  Issued one direction ahead of the arithmetic.
+struct MrRaw {
+    uint4 q[2][3];
+    float s[2];
+    uint4 l0;
+    uint2 l1;
+};
+
+// Per-lane A-fragment pattern, the same for every direction and pair: entry t of the
+// fragment is sign[t] * Ls[pair * 36 + off[t]] (sign 0: a zero of the block diagonal).
+struct MrAPattern {
+    int off[4];
+    float sign[4];
+};
+
+__device__ __forceinline__ MrAPattern mr_a_pattern(int lane)
 {
-    const uint4* p = (const uint4*)base;
+    MrAPattern a;
+    const int m = lane & 15, g = lane >> 4;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) unpack8<P>(p[(size_t)k * ps + cb], 1.0f, v + 8 * k);
-    return ((const float*)(p + (size_t)3 * ps))[cb];
+    for (int t = 0; t < 4; ++t) {
+        const int kk = 4 * g + t;
+        const bool ok = m < 12 && kk < 12 && m / 6 == kk / 6;
+        const int row_site = m / 6, ca = (m % 6) >> 1, c1 = m & 1, cb_ = (kk % 6) >> 1, c2 = kk & 1;
+        // [[Er, -Ei], [Ei, Er]]: the real part where c1 == c2, else the imaginary part
+        a.off[t] = ok ? row_site * 18 + 2 * (3 * ca + cb_) + (c1 == c2 ? 0 : 1) : 0;
+        a.sign[t] = ok ? ((c1 == 0 && c2 == 1) ? -1.f : 1.f) : 0.f;
+    }
+    return a;
+}
+
+template <int D, int P>
+__device__ __forceinline__ void mr_load(const DslashArgs& A, const char* in0, uint32_t cb, const int c[4], int lane,
+                                        MrRaw& x)
+{
+    constexpr int MU = D >> 1;
+    constexpr bool FWD = (D & 1) == 0;
+    const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+        const int r = (lane >> 3) + 8 * j;
+        const uint4* pl = (const uint4*)(in0 + (size_t)r * A.in_stride);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) x.q[j][k] = pl[(size_t)k * A.g.ps + nb];
+        x.s[j] = ((const float*)(pl + (size_t)3 * A.g.ps))[nb];
+    }
+    if (lane < MR_SITES) {
+        const int lpar = FWD ? A.par : 1 - A.par;
+        const uint4* grp = (const uint4*)(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P, 12) * A.g.ps);
+        const uint32_t lcb = FWD ? cb : nb;
+        x.l0 = grp[lcb];
+        x.l1 = ((const uint2*)(grp + (size_t)A.g.ps))[lcb];
+    }
 }
 
 template <int D, int P, bool DAG>
-__device__ __forceinline__ void mr_direction(const DslashArgs& A, const char* in0, uint32_t cb, const int c[4], int lane,
-                                             char* lds, float (&acc)[4][4][4])
+__device__ __forceinline__ void mr_compute(const DslashArgs& A, const int c[4], int lane, char* lds, const MrRaw& x,
+                                           const MrAPattern& ap, float (&acc)[4][4][4])
 {
     constexpr int MU = D >> 1;
     constexpr bool FWD = (D & 1) == 0;
@@ -70,15 +116,14 @@ __device__ __forceinline__ void mr_direction(const DslashArgs& A, const char* in
     _Float16* Bt = (_Float16*)lds;
     float* Ls = (float*)(lds + MR_B_BYTES);
     float* Sc = (float*)(lds + MR_B_BYTES + MR_L_BYTES);
-    const int sl = lane & 7;               // this lane's site within the wave
-    const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
-
-    // 1. half spinors of the neighbour, two rhs per lane
+    const int sl = lane & 7;
+    // 1. half spinors in code units -> fp16 B tiles; scales aside
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
         const int r = (lane >> 3) + 8 * j;
         float psi[24], h[12];
-        const float s = mr_load_codes<P>(in0 + (size_t)r * A.in_stride, A.g.ps, nb, psi);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) unpack8<P>(x.q[j][k], 1.0f, psi + 8 * k);
         project<MU, S>(psi, h);
         const int p = sl >> 1, q = sl & 1;
 #pragma unroll
@@ -91,14 +136,15 @@ __device__ __forceinline__ void mr_direction(const DslashArgs& A, const char* in
                 dst[k] = __builtin_bit_cast(uint32_t, v);
             }
         }
-        Sc[sl * MR_RHS + r] = s;
+        Sc[sl * MR_RHS + r] = x.s[j];
     }
-    // 2. the links of the wave's 8 sites, as E = U (forward) or U^dagger (backward), signed
+    // 2. links as E = U (forward) or U^dagger (backward), with the boundary sign
     if (lane < MR_SITES) {
         float u[18];
-        const int lpar = FWD ? A.par : 1 - A.par;
-        LinkIO<P, 12, false>::load(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P, 12) * A.g.ps, A.g.ps,
-                                   FWD ? cb : nb, u);
+        unpack8<P>(x.l0, 1.0f, u);
+        u[8] = h2f<P>(x.l1.x); u[9] = h2f<P>(x.l1.x >> 16);
+        u[10] = h2f<P>(x.l1.y); u[11] = h2f<P>(x.l1.y >> 16);
+        reconstruct_row2(u);
         const float sg = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -110,56 +156,56 @@ __device__ __forceinline__ void mr_direction(const DslashArgs& A, const char* in
             }
     }
     mr_wave_sync();
-    // 3. products: lane (g, n) holds A rows m = lane & 15, K columns 4g..4g+3; B and D rows
-    //    4g..4g+3 of column n = rhs
-    const int m = lane & 15, g = lane >> 4, n = lane & 15;
+    // 3. products and spin expansion
+    const int g = lane >> 4, n = lane & 15;
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
         half4_t af;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int kk = 4 * g + t;
-            float v = 0.f;
-            if (m < 12 && kk < 12 && m / 6 == kk / 6) {
-                const int site = 2 * p + m / 6;
-                const int a = (m % 6) >> 1, c1 = m & 1, b = (kk % 6) >> 1, c2 = kk & 1;
-                const float er = Ls[site * 18 + 2 * (3 * a + b)], ei = Ls[site * 18 + 2 * (3 * a + b) + 1];
-                v = c1 == 0 ? (c2 == 0 ? er : -ei) : (c2 == 0 ? ei : er);
-            }
-            af[t] = (_Float16)v;
-        }
+        for (int t = 0; t < 4; ++t) af[t] = (_Float16)(ap.sign[t] * Ls[p * 36 + ap.off[t]]);
         mr_f32x4 d[2];
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp) {
             const half4_t bf = *(const half4_t*)(Bt + ((p * 2 + sp) * MR_RHS + n) * MR_LD + 4 * g);
             d[sp] = __builtin_amdgcn_mfma_f32_16x16x16f16(af, bf, mr_f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         }
-        if (g < 3) {
-            // rows 4g, 4g+1 and 4g+2, 4g+3 are two complex values (site, colour)
+        if (g < 3)   // D rows 12..15 (g = 3) are the zero padding
 #pragma unroll
-            for (int z = 0; z < 2; ++z) {
-                const int row = 4 * g + 2 * z;
-                const float sc = Sc[(2 * p + row / 6) * MR_RHS + n];
-                const float w0r = d[0][2 * z] * sc, w0i = d[0][2 * z + 1] * sc;
-                const float w1r = d[1][2 * z] * sc, w1i = d[1][2 * z + 1] * sc;
-                acc[p][0][2 * z] += w0r;
-                acc[p][0][2 * z + 1] += w0i;
-                acc[p][1][2 * z] += w1r;
-                acc[p][1][2 * z + 1] += w1i;
-                const float ar = PJ::J2 == 0 ? w0r : w1r, ai = PJ::J2 == 0 ? w0i : w1i;
-                const float br = PJ::J3 == 0 ? w0r : w1r, bi = PJ::J3 == 0 ? w0i : w1i;
-                acc[p][2][2 * z] += umul_re<PJ::C2>(ar, ai);
-                acc[p][2][2 * z + 1] += umul_im<PJ::C2>(ar, ai);
-                acc[p][3][2 * z] += umul_re<PJ::C3>(br, bi);
-                acc[p][3][2 * z + 1] += umul_im<PJ::C3>(br, bi);
-            }
+        for (int z = 0; z < 2; ++z) {
+            const int row = 4 * g + 2 * z;
+            const int rs = row < 6 ? 0 : 1;               // site of the row within the pair
+            const float sc = Sc[(2 * p + rs) * MR_RHS + n];
+            const float w0r = d[0][2 * z] * sc, w0i = d[0][2 * z + 1] * sc;
+            const float w1r = d[1][2 * z] * sc, w1i = d[1][2 * z + 1] * sc;
+            acc[p][0][2 * z] += w0r;
+            acc[p][0][2 * z + 1] += w0i;
+            acc[p][1][2 * z] += w1r;
+            acc[p][1][2 * z + 1] += w1i;
+            const float ar = PJ::J2 == 0 ? w0r : w1r, ai = PJ::J2 == 0 ? w0i : w1i;
+            const float br = PJ::J3 == 0 ? w0r : w1r, bi = PJ::J3 == 0 ? w0i : w1i;
+            acc[p][2][2 * z] += umul_re<PJ::C2>(ar, ai);
+            acc[p][2][2 * z + 1] += umul_im<PJ::C2>(ar, ai);
+            acc[p][3][2 * z] += umul_re<PJ::C3>(br, bi);
+            acc[p][3][2 * z + 1] += umul_im<PJ::C3>(br, bi);
         }
     }
     mr_wave_sync();
 }
 
+// directions D..7, each one's loads issued before the previous one's arithmetic
+template <int D, int P, bool DAG>
+__device__ __forceinline__ void mr_pipe(const DslashArgs& A, const char* in0, uint32_t cb, const int c[4], int lane,
+                                        char* lds, const MrAPattern& ap, float (&acc)[4][4][4], MrRaw& cur, MrRaw& nxt)
+{
+    // compiler barrier: the loads of direction D + 1 may not move above the arithmetic of D - 1
+    asm volatile("" ::: "memory");
+    if constexpr (D < 7) mr_load<D + 1, P>(A, in0, cb, c, lane, nxt);
+    mr_compute<D, P, DAG>(A, c, lane, lds, cur, ap, acc);
+    if constexpr (D < 7) mr_pipe<D + 1, P, DAG>(A, in0, cb, c, lane, lds, ap, acc, nxt, cur);
+}
+
 template <int P, bool DAG, bool XPAY>
-__global__ void __launch_bounds__(256) dslash_mrhs_kernel(DslashArgs A)
+__global__ void __launch_bounds__(256, 2) dslash_mrhs_kernel(DslashArgs A)
 {
     __shared__ __attribute__((aligned(16))) char lds_all[4][MR_WAVE_BYTES];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -190,14 +236,10 @@ __global__ void __launch_bounds__(256) dslash_mrhs_kernel(DslashArgs A)
 #pragma unroll
             for (int k = 0; k < 4; ++k) acc[p][s][k] = 0.f;
     mr_wave_sync();
-    mr_direction<0, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<1, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<2, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<3, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<4, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<5, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<6, P, DAG>(A, in0, cb, c, lane, lds, acc);
-    mr_direction<7, P, DAG>(A, in0, cb, c, lane, lds, acc);
+    const MrAPattern ap = mr_a_pattern(lane);
+    MrRaw ra, rb;
+    mr_load<0, P>(A, in0, cb, c, lane, ra);
+    mr_pipe<0, P, DAG>(A, in0, cb, c, lane, lds, ap, acc, ra, rb);
     // accumulators -> [site][rhs][24] in LDS
     float* O = (float*)lds;
     const int g = lane >> 4, n = lane & 15;
