@@ -165,7 +165,8 @@ def extras(w, ctx, stream, torch, ls):
 def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245, tol=1e-10):
     """Time to an FP64-verified 1e-10 Wilson-system residual on 32^3 x 64 (eps 0.6,
     kappa 0.1245) through the even-odd CG, per inner (sloppy) storage precision,
-    plus the level where pure FP32 recurrences stall."""
+    the level where pure FP32 recurrences stall, and flexible GMRES on the Schur
+    complement without and with the learned preconditioner."""
     import ctypes
     X, Y, Z, T = dims
     g = w.Gauge(ctx, dims, BC, 12)
@@ -193,6 +194,27 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         d["seconds"] = round(d["seconds"], 5)
         d["seconds_first"] = round(secs[0], 5)
         d["delta"] = None if (pure or p == w.F64) else default_delta[p]
+        out[name] = d
+    # flexible GMRES on the Schur complement (FP32 cycles, FP64 refinement), without and with
+    # the network trained on 16^3 x 32 (applied here as trained: the layer is local)
+    from paper_0810_5365_amd import learn
+    net = learn.load_net(learn.DEFAULT_WEIGHTS, w.BF16)
+    ws = net.storage()
+    wid = (ctypes.c_int * len(net.widths))(*net.widths)
+    ptrs = (ctypes.c_void_p * len(ws))(*[t.data_ptr() for t in ws])
+    for name, nl in (("fgmres_f32", 0), ("fgmres_learned_f32", len(ws))):
+        secs = []
+        for rep in range(2):
+            fx = torch.zeros_like(fb)
+            prm = w.solver_params(tol=tol, maxiter=2000, sloppy=w.F32, delta=1e-4)
+            info = w.WdSolverInfo()
+            w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), 16, nl, wid if nl else None, ptrs if nl else None,
+                              net.wprec, fb.data_ptr(), fx.data_ptr(), ctypes.byref(info), ok=(w.WD_OK, w.WD_ENOCONV))
+            secs.append(info.seconds)
+        d = info.as_dict()
+        d["seconds"] = round(d["seconds"], 5)
+        d["seconds_first"] = round(secs[0], 5)
+        d["restart"], d["delta"] = 16, 1e-4
         out[name] = d
     g.close()
     return out

@@ -548,6 +548,75 @@ wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nh, int prec, const v
     return maxpy_any(ctx, g, nh, prec, V, vstride, k, coef, nullptr, 0.f, w, scale, out);
 }
 
+// Second Gram-Schmidt pass fused with the first pass's update: per site
+//   w' = w - sum_i h1_i V_i   (h1 from dres[slot1 ..], written back to w)
+//   partial <V_i, w'> for i < k and ||w'||^2, with V_i read once from HBM (the dots re-read
+//   the site's V_i from cache right after the update).  Up to MGS_KMAX vectors; the norm
+//   lands in value 2 MGS_KMAX.
+
+template <int P>
+__global__ void __launch_bounds__(RED_BLOCK) maxpy_mdot_kernel(SiteRange Vs, size_t vstride, int k, const double* h1,
+                                                               SiteRange W, long long nsites, double* partials)
+{
+    using T = typename RealOf<P>::T;
+    double acc[2 * MGS_KMAX + 1];
+#pragma unroll
+    for (int q = 0; q < 2 * MGS_KMAX + 1; ++q) acc[q] = 0.0;
+    for (long long s = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; s < nsites; s += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = s / W.Vh;
+        const uint32_t cb = (uint32_t)(s - h * W.Vh);
+        T w[24];
+        SpinorIO<P>::load(W.half(h), W.ps, cb, w);
+        for (int i = 0; i < k; ++i) {
+            T v[24];
+            SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, v);
+            const T cr = (T)(-(float)h1[2 * i]), ci = (T)(-(float)h1[2 * i + 1]);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                w[2 * q] += cr * v[2 * q] - ci * v[2 * q + 1];
+                w[2 * q + 1] += cr * v[2 * q + 1] + ci * v[2 * q];
+            }
+        }
+        SpinorIO<P>::store((char*)W.half(h), W.ps, cb, w);
+#pragma unroll
+        for (int i = 0; i < MGS_KMAX; ++i) {
+            if (i < k) {
+                T v[24];
+                SpinorIO<P>::load(Vs.half(h) + (size_t)i * vstride, W.ps, cb, v);
+#pragma unroll
+                for (int q = 0; q < 12; ++q) {
+                    const double ar = v[2 * q], ai = v[2 * q + 1], br = w[2 * q], bi = w[2 * q + 1];
+                    acc[2 * i] += ar * br + ai * bi;
+                    acc[2 * i + 1] += ar * bi - ai * br;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 24; ++q) acc[2 * MGS_KMAX] += (double)w[q] * (double)w[q];
+    }
+    block_reduce<2 * MGS_KMAX + 1>(acc, partials);
+}
+
+wd_status blas_maxpy_mdot(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
+                          int slot1, void* w)
+{
+    if (k < 1 || k > MGS_KMAX || slot1 < 2 * MGS_KMAX + 1 || slot1 + 2 * k > 256) {
+        set_error("maxpy_mdot: k = %d (slot %d) out of range", k, slot1);
+        return WD_EINVAL;
+    }
+    const long long ns = (long long)nh * g.Vh;
+    const int nblk = red_blocks(ns);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * (2 * MGS_KMAX + 1)));
+    SiteRange Vs{(const char*)V, g.Vh, g.ps, half_bytes(g, prec)}, W{(const char*)w, g.Vh, g.ps, half_bytes(g, prec)};
+    switch (prec) {
+    case WD_F32: hipLaunchKernelGGL(maxpy_mdot_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, Vs, vstride, k,
+                                    (const double*)(ctx->dres + slot1), W, ns, ctx->partials); break;
+    default: set_error("maxpy_mdot: precision %d not supported (F32 only)", prec); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return finish(ctx, nblk, 2 * MGS_KMAX + 1, true);
+}
+
 wd_status blas_maxpy_dev(wd_context ctx, const Geom& g, size_t nh, int prec, const void* V, size_t vstride, int k,
                          int slot, float sign, const void* w, double scale, void* out)
 {

@@ -143,9 +143,16 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
             // pass (with ||w||^2 in the same reduction) waits for the host
             constexpr int SLOT_H1 = 128;
             WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, false, false, SLOT_H1));
-            WD_TRY(blas_maxpy_dev(ctx, G, nh, WD_F32, V, v32, j + 1, SLOT_H1, -1.0f, wv, 1.0, wv));
-            WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
-            const double w2 = ctx->hres[2 * (j + 1)];
+            int norm_at = 2 * (j + 1);
+            if (j + 1 <= MGS_KMAX) {
+                // the first pass's update and the second pass's dots in one sweep over V
+                WD_TRY(blas_maxpy_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, SLOT_H1, wv));
+                norm_at = 2 * MGS_KMAX;
+            } else {
+                WD_TRY(blas_maxpy_dev(ctx, G, nh, WD_F32, V, v32, j + 1, SLOT_H1, -1.0f, wv, 1.0, wv));
+                WD_TRY(blas_mdot(ctx, G, nh, WD_F32, V, v32, j + 1, wv, true, true));
+            }
+            const double w2 = ctx->hres[norm_at];
             double h2 = 0.0;
             std::vector<double> coef(2 * (j + 1));
             for (int i = 0; i <= j; ++i) {

@@ -158,6 +158,11 @@ wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, con
 constexpr int WD_MAXPY = 64;
 wd_status blas_maxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
                      const double* coef, const void* w, double scale, void* out);
+// w -= sum_i h1_i V_i (h1 = dres[slot1 ..], float-rounded as in blas_maxpy_dev), then
+// <V_i, w> in dres/hres[2i], [2i + 1] for i < k <= MGS_KMAX and ||w||^2 in [2 MGS_KMAX]; fetched
+constexpr int MGS_KMAX = 16;
+wd_status blas_maxpy_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
+                          int slot1, void* w);
 // the same with c_i = sign (dres[slot + 2i], dres[slot + 2i + 1]) read on the device (no host round trip)
 wd_status blas_maxpy_dev(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
                          int slot, float sign, const void* w, double scale, void* out);
