@@ -280,14 +280,16 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
  * stack of nlayers parallel-transport convolutions with channel widths
  * widths[0..nlayers] (widths[0] = widths[nlayers] = 4: spin as channels) and
  * weights[l] the [9][widths[l+1]][widths[l]] complex weights at wprec (device
- * pointers); nlayers = 0 runs unpreconditioned GMRES on Mhat.  Cycles of at
- * most `restart` iterations run in float32 on rhat_e = r_e + kappa D_eo r_o and
- * stop when their residual estimate has fallen by params->delta (> 0; else
- * 1e-4); x (both parities) and the true residual b - M x are updated in
- * float64 after each cycle, and the solve ends when ||b - M x|| / ||b|| <=
- * params->tol.  A NaN or a cycle that reduces the true residual less than
- * tenfold hands x to wd_wilson_solve (fell_back = 1), whose float64 residual
- * is reported.
+ * pointers); nlayers = 0 runs unpreconditioned GMRES on Mhat.  Only the even
+ * half of the initial guess is used.  Cycles of at most `restart` iterations
+ * run in float32 on rhat = bhat - Mhat x_e (bhat = b_e + kappa D_eo b_o, both in
+ * float64) and stop when their residual estimate has fallen by params->delta
+ * (> 0; else 1e-4); x_e and rhat are updated in float64 after each cycle until
+ * ||rhat|| / ||b|| <= params->tol; then x_o = b_o + kappa D_oe x_e, and the full
+ * residual ||b - M x|| / ||b||, recomputed in float64, is reported (it equals
+ * ||rhat|| / ||b|| up to rounding).  A NaN or a cycle that reduces the residual
+ * less than tenfold hands x to wd_wilson_solve (fell_back = 1), whose float64
+ * residual is reported.
  * restart must be in [1, 63].  Synchronous. */
 wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
                           const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
