@@ -195,6 +195,20 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         d["seconds_first"] = round(secs[0], 5)
         d["delta"] = None if (pure or p == w.F64) else default_delta[p]
         out[name] = d
+    # BiCGstab on the Schur complement (FP32 iterations, FP64 reliable updates)
+    for name, p in (("bicgstab_f32", w.F32),):
+        secs = []
+        for rep in range(2):
+            fx = torch.zeros_like(fb)
+            prm = w.solver_params(tol=tol, maxiter=5000, sloppy=p, delta=-1.0)
+            info = w.WdSolverInfo()
+            w.wd_bicgstab_solve(g.handle, kappa, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
+                                ok=(w.WD_OK, w.WD_ENOCONV))
+            secs.append(info.seconds)
+        d = {k: v for k, v in info.as_dict().items() if k not in ("cycles", "fell_back")}
+        d["seconds"] = round(d["seconds"], 5)
+        d["seconds_first"] = round(secs[0], 5)
+        out[name] = d
     # flexible GMRES on the Schur complement (FP32 cycles, FP64 refinement), without and with
     # the network trained on 16^3 x 32 (applied here as trained: the layer is local)
     from paper_0810_5365_amd import learn
@@ -220,6 +234,34 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
     return out
 
 
+def network_layer_times(w, ctx, net, dims, reps=100):
+    """Each layer of the committed network (bf16 weights, matrix-core mixing) on random
+    features over the whole lattice: microseconds per launch (HIP events on the stream)."""
+    import torch
+    import lattice_synth as ls
+    f = __import__("paper_0810_5365_amd.learn", fromlist=["Field"]).Field(ctx, dims, 0.7, 6001)
+    stream = torch.cuda.current_stream(0)
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    gen = torch.Generator().manual_seed(7)
+    res = {}
+    for (cin, cout), Ws in zip(zip(net.widths[:-1], net.widths[1:]), net.storage()):
+        x = torch.randn(cin * 6 * V, generator=gen).cuda()
+        y = torch.empty(cout * 6 * V, device="cuda")
+        run = lambda: w.wd_ptconv_forward(f.g.handle, cin, cout, net.wprec, 1, Ws.data_ptr(), x.data_ptr(), y.data_ptr())
+        for _ in range(5):
+            run()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res["%d->%d" % (cin, cout)] = round(e0.elapsed_time(e1) * 1e3 / reps, 2)
+    f.close()
+    return {"lattice": list(dims), "us_per_launch": res,
+            "unique_bytes_per_site": {k: (int(k.split("->")[0]) + int(k.split("->")[1])) * 24 + 4 * 48 for k in res}}
+
+
 def learned_extras(w, ctx):
     """Time to an FP64-verified 1e-10 Wilson-system residual on 16^3 x 32 (eps 0.7, kappa 0.1248),
     four gauge fields unseen in training: plain FP32 CG (with FP64 reliable updates), flexible
@@ -242,6 +284,7 @@ def learned_extras(w, ctx):
         out["mean_" + k] = {"iters": float(np.mean([r[k]["iters"] for r in rows])),
                             "wall_ms": round(1e3 * float(np.mean([r[k]["wall_s"] for r in rows])), 3)}
     out["learned_speedup_vs_plain_cg"] = round(out["mean_plain_cg_f32"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
+    out["network_layers"] = network_layer_times(w, ctx, net, dims)
     out["learned_speedup_vs_fgmres_no_net"] = round(out["mean_fgmres_no_net"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
     return out
 
