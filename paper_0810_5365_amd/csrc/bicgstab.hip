@@ -56,42 +56,55 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     bool dirty = false;
     wd_status status = WD_ENOCONV;
     if (rr <= target) status = WD_OK;
+    // Each iteration: 2 operator applications and 5 fused sweeps, 3 of them reductions the host
+    // waits for (<r0, v>; <t, s> with ||t||^2; ||r||^2 with <r0, r> from the r update itself).
+    cd rho_new;
+    bool have_rho = false;
     while (status != WD_OK && info->iters < prm.maxiter) {
-        cd rho_new;
-        WD_TRY(dot(r0, rs, &rho_new));
+        if (!have_rho) WD_TRY(dot(r0, rs, &rho_new));
         if (!std::isfinite(rho_new.real()) || std::abs(rho_new) == 0.0) {
             set_error("BiCGstab breakdown: rho = 0 at iteration %d", info->iters);
             status = WD_ENAN;
             break;
         }
         const cd beta = (rho_new / rho) * (alpha / omega);
-        // p = r + beta (p - omega v)
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, -omega.real(), -omega.imag(), v, 1.0, 0.0, p));
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, 1.0, 0.0, rs, beta.real(), beta.imag(), p));
+        {   // p = r + beta (p - omega v)
+            const cd c2 = -beta * omega;
+            const void* in[3] = {rs, p, v};
+            const double cr[3] = {1.0, beta.real(), c2.real()}, ci[3] = {0.0, beta.imag(), c2.imag()};
+            WD_TRY(blas_lincomb(ctx, G, 1, ps, 3, in, cr, ci, p, nullptr, false));
+        }
         WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, p, v));
         cd r0v;
         WD_TRY(dot(r0, v, &r0v));
         alpha = rho_new / r0v;
-        // s = r - alpha v
-        WD_TRY(launch_convert(ctx, G, 1, ps, rs, ps, s));
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, -alpha.real(), -alpha.imag(), v, 1.0, 0.0, s));
+        {   // s = r - alpha v
+            const void* in[2] = {rs, v};
+            const double cr[2] = {1.0, -alpha.real()}, ci[2] = {0.0, -alpha.imag()};
+            WD_TRY(blas_lincomb(ctx, G, 1, ps, 2, in, cr, ci, s, nullptr, false));
+        }
         WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, s, t));
         info->operator_applies += 2;
-        cd ts;
-        WD_TRY(dot(t, s, &ts));
-        WD_TRY(blas_norm2(ctx, G, 1, ps, t, true));
-        const double tt = ctx->hres[0];
+        WD_TRY(blas_dot_norm(ctx, G, 1, ps, t, s, true));
+        const cd ts(ctx->hres[0], ctx->hres[1]);
+        const double tt = ctx->hres[2];
         omega = tt > 0.0 ? ts / tt : cd(0.0);
-        // x_s += alpha p + omega s ; r = s - omega t
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, alpha.real(), alpha.imag(), p, 1.0, 0.0, xs));
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, omega.real(), omega.imag(), s, 1.0, 0.0, xs));
-        WD_TRY(blas_cxpby(ctx, G, 1, ps, -omega.real(), -omega.imag(), t, 1.0, 0.0, s));
-        std::swap(rs, s);
+        {   // x_s += alpha p + omega s
+            const void* in[3] = {xs, p, s};
+            const double cr[3] = {1.0, alpha.real(), omega.real()}, ci[3] = {0.0, alpha.imag(), omega.imag()};
+            WD_TRY(blas_lincomb(ctx, G, 1, ps, 3, in, cr, ci, xs, nullptr, false));
+        }
+        {   // r = s - omega t, with ||r||^2 and <r0, r> (the next rho)
+            const void* in[2] = {s, t};
+            const double cr[2] = {1.0, -omega.real()}, ci[2] = {0.0, -omega.imag()};
+            WD_TRY(blas_lincomb(ctx, G, 1, ps, 2, in, cr, ci, rs, r0, true));
+        }
         dirty = true;
         rho = rho_new;
         info->iters++;
-        WD_TRY(blas_norm2(ctx, G, 1, ps, rs, true));
         double rr_s = ctx->hres[0];
+        rho_new = cd(ctx->hres[1], ctx->hres[2]);
+        have_rho = true;
         if (!std::isfinite(rr_s) || std::abs(omega) == 0.0) {
             set_error("BiCGstab breakdown at iteration %d", info->iters);
             status = WD_ENAN;
@@ -108,6 +121,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
                 break;
             }
             WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, rs));
+            have_rho = false;   // r changed: rho = <r0, r> again
             maxrr = rr;
         } else if (rr_s > maxrr) {
             maxrr = rr_s;

@@ -428,6 +428,126 @@ wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nh, int prec, double 
     return WD_OK;
 }
 
+// ---- fused linear combinations (BiCGstab) ------------------------------------------------
+// out = sum_{i < n} c_i X_i (complex c_i, n <= 3; out may be one of the X_i).  RED adds the
+// reductions ||out||^2 and <R0, out> (values 0, 1, 2 = ||out||^2, Re, Im), so one sweep both
+// updates a vector and produces the next iteration's scalars.
+struct Lincomb {
+    SiteRange X[3];
+    double cr[3], ci[3];
+    int n;
+};
+
+template <int P, bool RED>
+__global__ void __launch_bounds__(RED_BLOCK) lincomb_kernel(Lincomb L, SiteRange O, SiteRange R0, long long nsites,
+                                                            double* partials)
+{
+    using T = typename RealOf<P>::T;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long s = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; s < nsites; s += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = s / O.Vh;
+        const uint32_t cb = (uint32_t)(s - h * O.Vh);
+        T o[24];
+#pragma unroll
+        for (int q = 0; q < 24; ++q) o[q] = 0;
+        for (int i = 0; i < L.n; ++i) {
+            T x[24];
+            SpinorIO<P>::load(L.X[i].half(h), O.ps, cb, x);
+            const T ar = (T)L.cr[i], ai = (T)L.ci[i];
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                o[2 * q] += ar * x[2 * q] - ai * x[2 * q + 1];
+                o[2 * q + 1] += ar * x[2 * q + 1] + ai * x[2 * q];
+            }
+        }
+        SpinorIO<P>::store((char*)O.half(h), O.ps, cb, o);
+        if constexpr (RED) {
+            T r0[24];
+            SpinorIO<P>::load(R0.half(h), O.ps, cb, r0);
+#pragma unroll
+            for (int q = 0; q < 12; ++q) {
+                const double orr = o[2 * q], oi = o[2 * q + 1], ar = r0[2 * q], ai = r0[2 * q + 1];
+                acc[0] += orr * orr + oi * oi;
+                acc[1] += ar * orr + ai * oi;
+                acc[2] += ar * oi - ai * orr;
+            }
+        }
+    }
+    if constexpr (RED) block_reduce<3>(acc, partials);
+}
+
+wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nh, int prec, int n, const void* const* x,
+                       const double* cre, const double* cim, void* out, const void* r0, bool fetch)
+{
+    if (n < 1 || n > 3) {
+        set_error("lincomb: %d inputs (1..3)", n);
+        return WD_EINVAL;
+    }
+    Lincomb L;
+    L.n = n;
+    const size_t hb = half_bytes(g, prec);
+    for (int i = 0; i < 3; ++i) {
+        L.X[i] = SiteRange{(const char*)(i < n ? x[i] : out), g.Vh, g.ps, hb};
+        L.cr[i] = i < n ? cre[i] : 0.0;
+        L.ci[i] = i < n ? cim[i] : 0.0;
+    }
+    SiteRange O{(const char*)out, g.Vh, g.ps, hb}, R{(const char*)(r0 ? r0 : out), g.Vh, g.ps, hb};
+    const long long ns = (long long)nh * g.Vh;
+    const int nblk = red_blocks(ns);
+    if (r0) WD_TRY(ensure_reduction(ctx, (size_t)nblk * 3));
+#define WD_LC(PP)                                                                                                   \
+    if (r0) hipLaunchKernelGGL((lincomb_kernel<PP, true>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, L, O, R, ns,   \
+                               ctx->partials);                                                                       \
+    else hipLaunchKernelGGL((lincomb_kernel<PP, false>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, L, O, R, ns,     \
+                            ctx->partials);
+    switch (prec) {
+    case WD_F64: WD_LC(P_F64) break;
+    case WD_F32: WD_LC(P_F32) break;
+    default: set_error("lincomb: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    }
+#undef WD_LC
+    WD_LAUNCHED();
+    if (r0) return finish(ctx, nblk, 3, fetch);
+    return WD_OK;
+}
+
+// <a, b> (values 0, 1) and ||a||^2 (value 2) in one sweep
+template <int P>
+__global__ void __launch_bounds__(RED_BLOCK) dot_norm_kernel(SiteRange A, SiteRange B, long long nsites, double* partials)
+{
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = k / A.Vh;
+        const uint32_t cb = (uint32_t)(k - h * A.Vh);
+        typename RealOf<P>::T a[24], b[24];
+        SpinorIO<P>::load(A.half(h), A.ps, cb, a);
+        SpinorIO<P>::load(B.half(h), A.ps, cb, b);
+#pragma unroll
+        for (int i = 0; i < 12; ++i) {
+            const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+            acc[0] += ar * br + ai * bi;
+            acc[1] += ar * bi - ai * br;
+            acc[2] += ar * ar + ai * ai;
+        }
+    }
+    block_reduce<3>(acc, partials);
+}
+
+wd_status blas_dot_norm(wd_context ctx, const Geom& g, size_t nh, int prec, const void* a, const void* b, bool fetch)
+{
+    const long long n = (long long)nh * g.Vh;
+    const int nblk = red_blocks(n);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 3));
+    SiteRange A{(const char*)a, g.Vh, g.ps, half_bytes(g, prec)}, B{(const char*)b, g.Vh, g.ps, half_bytes(g, prec)};
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL(dot_norm_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
+    case WD_F32: hipLaunchKernelGGL(dot_norm_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
+    default: set_error("dot_norm: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    }
+    WD_LAUNCHED();
+    return finish(ctx, nblk, 3, fetch);
+}
+
 // ---- block Gram-Schmidt helpers (flexible GMRES) ---------------------------------------
 // <V_i, w> for i < k, and (with_norm) ||w||^2 as value k.  Vectors go in groups of four:
 // w is read once per group, so a pass reads k + ceil((k + 1) / 4) fields instead of 2 (k + 1).

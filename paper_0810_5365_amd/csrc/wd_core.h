@@ -150,6 +150,12 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
+// out = sum_{i < n} (cre[i] + i cim[i]) x[i], n <= 3, out may alias an input; with r0 non-null also
+// ||out||^2 and <r0, out> (dres/hres 0; 1, 2)
+wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nhalves, int prec, int n, const void* const* x,
+                       const double* cre, const double* cim, void* out, const void* r0, bool fetch);
+// <a, b> (dres/hres 0, 1) and ||a||^2 (2) in one sweep
+wd_status blas_dot_norm(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, const void* b, bool fetch);
 // h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[slot + 2i],
 // dres[slot + 2i + 1] (and hres); with_norm adds ||w||^2 in dres[slot + 2k]
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
