@@ -196,7 +196,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         d["delta"] = None if (pure or p == w.F64) else default_delta[p]
         out[name] = d
     # BiCGstab on the Schur complement (FP32 iterations, FP64 reliable updates)
-    for name, p in (("bicgstab_f32", w.F32),):
+    for name, p in (("bicgstab_f32", w.F32), ("bicgstab_f16", w.F16), ("bicgstab_bf16", w.BF16)):
         secs = []
         for rep in range(2):
             fx = torch.zeros_like(fb)

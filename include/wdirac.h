@@ -265,9 +265,10 @@ wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t byte
 
 /* Solve M x = b on the full lattice through the even-odd Schur complement with
  * BiCGstab on Mhat x_e = b_e + kappa D_eo b_o (paper, Section 7: the second
- * inverter).  params->sloppy must be F32 or F64; reliable updates recompute
- * bhat - Mhat x in float64 when the iterated residual drops below delta times
- * its running maximum.  true_resid is ||bhat - Mhat x_e|| / ||b||,
+ * inverter).  The iteration's vectors are stored at params->sloppy (F64, F32,
+ * or 16-bit with the per-site scale; arithmetic in float32, float64 for F64);
+ * reliable updates recompute bhat - Mhat x in float64 when the iterated
+ * residual drops below delta times its running maximum.  true_resid is ||bhat - Mhat x_e|| / ||b||,
  * true_resid_M the full-system ||b - M x|| / ||b||.  Synchronous. */
 wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
                             wd_solver_info* info);

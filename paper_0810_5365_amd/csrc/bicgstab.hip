@@ -18,7 +18,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
-    const int ps = prm.sloppy == WD_F64 ? WD_F64 : WD_F32;
+    const int ps = prm.sloppy;   // storage of the iteration's vectors; arithmetic in float32 (float64 for F64)
     const double delta = resolve_delta(prm.delta, ps);
     const size_t hs = half_bytes(G, ps), h64 = half_bytes(G, WD_F64);
     void *r, *t64, *rs, *r0, *p, *v, *s, *t, *xs;
@@ -148,10 +148,6 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     if (!(params->tol > 0.0) || params->maxiter < 0 || !valid_prec(params->sloppy) || !(params->delta < 1.0)) {
         set_error("wd_bicgstab_solve: bad solver params");
         return WD_EINVAL;
-    }
-    if (params->sloppy == WD_F16 || params->sloppy == WD_BF16) {
-        set_error("wd_bicgstab_solve: sloppy precision must be F32 or F64");
-        return WD_EUNSUPPORTED;
     }
     if (!g->uploaded) {
         set_error("gauge field has not been uploaded");

@@ -503,7 +503,9 @@ wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nh, int prec, int n
     switch (prec) {
     case WD_F64: WD_LC(P_F64) break;
     case WD_F32: WD_LC(P_F32) break;
-    default: set_error("lincomb: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    case WD_F16: WD_LC(P_F16) break;
+    case WD_BF16: WD_LC(P_BF16) break;
+    default: set_error("lincomb: bad precision %d", prec); return WD_EINVAL;
     }
 #undef WD_LC
     WD_LAUNCHED();
@@ -542,7 +544,9 @@ wd_status blas_dot_norm(wd_context ctx, const Geom& g, size_t nh, int prec, cons
     switch (prec) {
     case WD_F64: hipLaunchKernelGGL(dot_norm_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
     case WD_F32: hipLaunchKernelGGL(dot_norm_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
-    default: set_error("dot_norm: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
+    case WD_F16: hipLaunchKernelGGL(dot_norm_kernel<P_F16>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
+    case WD_BF16: hipLaunchKernelGGL(dot_norm_kernel<P_BF16>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
+    default: set_error("dot_norm: bad precision %d", prec); return WD_EINVAL;
     }
     WD_LAUNCHED();
     return finish(ctx, nblk, 3, fetch);

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 BC = (1, 1, 1, -1)
 
 
-@pytest.mark.parametrize("sloppy", ["f64", "f32"])
+@pytest.mark.parametrize("sloppy", ["f64", "f32", "f16", "bf16"])
 def test_bicgstab_wilson_system(sloppy):
     import torch
     from paper_0810_5365_amd import wdirac as w
@@ -37,7 +37,7 @@ def test_bicgstab_wilson_system(sloppy):
     ctx.close()
 
 
-def test_bicgstab_rejects_16bit_sloppy():
+def test_bicgstab_rejects_bad_params():
     from paper_0810_5365_amd import wdirac as w
     dims = (4, 4, 4, 4)
     ctx = w.Context(0)
@@ -45,9 +45,9 @@ def test_bicgstab_rejects_16bit_sloppy():
     g.upload(ls.gauge_field(dims, 0.5, 1))
     lat = w.lattice(dims, BC)
     f = w.new_field(lat, w.FULL, w.F64)
-    prm = w.solver_params(sloppy=w.BF16)
     info = w.WdSolverInfo()
-    assert w._raw().wd_bicgstab_solve(g.handle, 0.1, ctypes.byref(prm), f.data_ptr(), f.data_ptr(),
-                                      ctypes.byref(info)) == w.WD_EUNSUPPORTED
+    for prm in (w.solver_params(sloppy=7), w.solver_params(tol=-1.0), w.solver_params(delta=1.5)):
+        assert w._raw().wd_bicgstab_solve(g.handle, 0.1, ctypes.byref(prm), f.data_ptr(), f.data_ptr(),
+                                          ctypes.byref(info)) == w.WD_EINVAL
     g.close()
     ctx.close()
