@@ -127,8 +127,10 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
             maxrr = rr_s;
         }
     }
-    if (dirty) WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
-    WD_TRY(true_res(&rr));
+    if (dirty) {   // else rr is that of the last reliable update, already of this x
+        WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
+        WD_TRY(true_res(&rr));
+    }
     info->true_resid = std::sqrt(rr / bnorm2);
     if (status != WD_ENAN) status = rr <= target ? WD_OK : WD_ENOCONV;
     return status;

@@ -139,9 +139,11 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
             rr_s = rr_new;
         }
     }
-    if (xs_dirty) WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
-    WD_TRY(true_residual(P, x, r, &rr, &ww));
-    info->operator_applies++;
+    if (xs_dirty) {   // else rr, ww are those of the last reliable update, already of this x
+        WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+        WD_TRY(true_residual(P, x, r, &rr, &ww));
+        info->operator_applies++;
+    }
     info->true_resid = std::sqrt(rr / cc);
     info->true_resid_M = P.bhat ? std::sqrt(ww / P.wnorm2) : -1.0;
     if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
