@@ -77,6 +77,33 @@ def test_fgmres_with_network(env, wprec):
     assert res <= 1.05e-10, (res, info.as_dict())
 
 
+def test_fgmres_long_cycles(env):
+    """A cycle longer than 16 iterations takes the unfused second Gram-Schmidt pass: with a
+    cycle target it cannot reach in float32 and an iteration cap of 17 the first cycle runs
+    exactly 17 iterations; its update must still be the least-squares one (residual checked
+    by the FP64 oracle), and a full solve with long cycles reaches the tolerance."""
+    import torch
+    w, ctx, dims, U, g = env
+    _LINKS[dims] = U
+    lat = w.lattice(dims, BC)
+    X, Y, Z, T = dims
+    b = ls.gaussian_complex((T, Z, Y, X, 4, 3), 11, ls.STREAM_SPINOR)
+    fb = w.pack(ctx, lat, w.FULL, w.F64, b)
+    for maxiter, delta in ((17, 1e-12), (3000, 1e-9)):
+        fx = torch.zeros_like(fb)
+        prm = w.solver_params(tol=1e-10, maxiter=maxiter, sloppy=w.F32, delta=delta)
+        info = w.WdSolverInfo()
+        w.wd_fgmres_solve(g.handle, 0.1248, ctypes.byref(prm), 40, 0, None, None, w.F32, fb.data_ptr(), fx.data_ptr(),
+                          ctypes.byref(info), ok=(w.WD_OK, w.WD_ENOCONV))
+        x = w.unpack(ctx, lat, w.FULL, w.F64, fx, b.shape)
+        res = orc.rel_residual(lambda v: orc.apply_m(U, v, 0.1248, BC), x, b)
+        assert info.fell_back == 0 and abs(res - info.true_resid_M) < 1e-12, info.as_dict()
+        if maxiter == 17:
+            assert info.iters == 17 and info.cycles == 1 and res < 1e-6, (res, info.as_dict())
+        else:
+            assert info.status == w.WD_OK and res <= 1.05e-10, (res, info.as_dict())
+
+
 def test_fgmres_parity_skips_change_nothing(env, monkeypatch):
     """The network's first layer skips paths that read the zero odd half of (v_e, 0), the last
     computes only even sites; with bf16 weights on the matrix cores the skipped terms are exact
