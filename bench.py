@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--dims", type=int, nargs=4, default=list(DIMS))
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-rhs and ragged-batch measurements")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the L^3 x 2L volume sweep")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning table: loaded if it exists (no tuning), else tuned and written there")
     return ap.parse_args()
@@ -85,7 +86,170 @@ def cpu_baseline(U, psi_e, dims):
     flops = Vh * 2 * (2 * FLOPS_DSLASH + FLOPS_XPAY)
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": "%d application(s) of the FP64 oracle's Mhat^dag Mhat on the full %dx%dx%dx%d lattice "
-                      "(%d even sites), %.2f s each" % (reps, *dims, Vh, dt)}
+                      "(%d even sites), %.2f s each" % (reps, *dims, Vh, dt),
+            "one_core": cpu_one_core()}
+
+
+_ONE_CORE = r"""
+import sys, time
+sys.path.insert(0, sys.argv[1])
+import lattice_synth as ls, oracle as orc
+dims = (16, 16, 16, 32)
+U = ls.gauge_field(dims, 0.5, ls.link_seed(2))
+psi = ls.gaussian_complex((16 * 16 * 16 * 16, 4, 3), ls.source_seed(2), ls.STREAM_SPINOR)
+orc.mhat_dag_mhat(U, psi, 0.124, (1, 1, 1, -1))
+t0 = time.perf_counter()
+orc.mhat_dag_mhat(U, psi, 0.124, (1, 1, 1, -1))
+print(orc.num_threads(), time.perf_counter() - t0)
+"""
+
+
+def cpu_one_core():
+    """The same oracle operator on one thread (a child process with OMP_NUM_THREADS=1),
+    on 16^3 x 32 to keep it to a few seconds."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", HIP_VISIBLE_DEVICES="")
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        out = subprocess.run([sys.executable, "-c", _ONE_CORE, root], env=env, capture_output=True, text=True,
+                             timeout=300, check=True).stdout.split()
+    except (subprocess.SubprocessError, OSError) as e:
+        return {"error": str(e)[:200]}
+    threads, dt = int(out[0]), float(out[1])
+    Vh = 16 * 16 * 16 * 16
+    return {"value": round(Vh * 2 * (2 * FLOPS_DSLASH + FLOPS_XPAY) / dt / 1e9, 3), "unit": "GFLOP/s",
+            "cores": threads, "sample": "1 application of Mhat^dag Mhat on 16x16x16x32, %.2f s" % dt}
+
+
+def plaquette(U):
+    """Average plaquette (1/3) Re tr U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag over
+    sites and the six planes, periodic wrap (a property of the gauge field alone,
+    reported beside each solve)."""
+    import numpy as np
+    axis = {0: 3, 1: 2, 2: 1, 3: 0}   # mu = x, y, z, t -> array axis of (T, Z, Y, X)
+    tot = 0.0
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            a = U[mu] @ np.roll(U[nu], -1, axis[mu])
+            b = U[nu] @ np.roll(U[mu], -1, axis[nu])
+            tot += float((a * b.conj()).real.sum())   # Re tr(a b^dag)
+    return float(tot / (6 * 3 * U[0].shape[0] * U[0].shape[1] * U[0].shape[2] * U[0].shape[3]))
+
+
+def timed_repeats(fn, stream, torch, n=100, repeats=5, warmup=10):
+    """Median and minimum over `repeats` runs of n back-to-back calls (HIP events on
+    the stream), microseconds per call."""
+    import numpy as np
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    us = []
+    for _ in range(repeats):
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        us.append(e0.elapsed_time(e1) * 1e3 / n)
+    return float(np.median(us)), float(min(us))
+
+
+def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20):
+    """FP32 12-real EO dslash on L^3 x 2L lattices: warm (5 x 100 back-to-back launches,
+    median and minimum) and, where the compulsory working set fits the 256 MB
+    last-level cache, single launches timed alone, warm and cold (after 1 GiB of
+    other traffic).  The links
+    are the sub-box of the 32^3 x 64 field: i.i.d. per link, so each is a field of
+    the same distribution."""
+    import numpy as np
+    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    scrub2 = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    rows = []
+    for L in sizes:
+        dims = (L, L, L, 2 * L)
+        Vh = L ** 3 * L
+        if 2 * L > U.shape[1] or L > U.shape[4]:
+            continue
+        g = w.Gauge(ctx, dims, BC, w.RECON_12)
+        g.upload(np.ascontiguousarray(U[:, :2 * L, :L, :L, :L]))
+        g.prepare(w.F32)
+        lat = w.lattice(dims, BC)
+        fin = w.pack(ctx, lat, w.ODD, w.F32, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, L), ls.STREAM_SPINOR))
+        fout = w.new_field(lat, w.EVEN, w.F32)
+        w.wd_autotune_dslash(g.handle, w.F32, 1, None)
+        run = lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fin.data_ptr(), fout.data_ptr())
+        med, mn = timed_repeats(run, stream, torch)
+        ws = Vh * BYTES_DSLASH
+        row = {"L": L, "lattice": "%dx%dx%dx%d" % dims, "even_sites": Vh, "working_set_mb": round(ws / 1e6, 1),
+               "warm_us_median": round(med, 3), "warm_us_min": round(mn, 3),
+               "warm_gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1),
+               "warm_frac_hbm": round(ws / med / 1e3 / HBM_PEAK_GBS, 4)}
+        if ws < mall_bytes:
+            # one launch at a time between events: first with the data left in the caches by
+            # the previous launch, then after evicting it (a 1 GiB write, then a 1 GiB read so
+            # that no dirty lines of the write are still being written back)
+            single = {}
+            for mode in ("warm_single", "cold"):
+                t = []
+                for _ in range(20):
+                    if mode == "cold":
+                        scrub.fill_(1)
+                        scrub2.sum()
+                    else:
+                        run()
+                    e0.record(stream)
+                    run()
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    t.append(e0.elapsed_time(e1) * 1e3)
+                single[mode] = float(np.median(t))
+                row.update({mode + "_us_median": round(single[mode], 3), mode + "_us_min": round(min(t), 3)})
+            row.update({"cold_gflops": round(Vh * FLOPS_DSLASH / single["cold"] / 1e3, 1),
+                        "cold_frac_hbm": round(ws / single["cold"] / 1e3 / HBM_PEAK_GBS, 4)})
+        rows.append(row)
+        del fin, fout
+        g.close()
+    del scrub, scrub2
+    return {"kernel": "dslash_kernel<F32, r12>, autotuned per size", "bytes_per_site": BYTES_DSLASH, "rows": rows}
+
+
+def slab_extras(w, ctx, stream, torch, ls, U, nslab=8, link_gbs=153.0):
+    """One device's share of the 32^3 x 64 lattice split into `nslab` t-slabs: the
+    slab dslash with half-spinor faces (F32, 12-real links) against the ordinary
+    dslash on the same slab, the face packing, and the bytes each face sends.
+    The transfer time is modelled at one inter-device link per face direction
+    (about 153 GB/s each); on one device the faces are copies of its own."""
+    import numpy as np
+    X, Y, Z, T = DIMS
+    Tl = T // nslab
+    dims = (X, Y, Z, Tl)
+    Vh = X * Y * Z * Tl // 2
+    g = w.Gauge(ctx, dims, BC, w.RECON_12)
+    g.upload(np.ascontiguousarray(U[:, :Tl]))
+    g.prepare(w.F32)
+    lat = w.lattice(dims, BC)
+    fin = w.pack(ctx, lat, w.ODD, w.F32, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 99), ls.STREAM_SPINOR))
+    fout = w.new_field(lat, w.EVEN, w.F32)
+    ff, fb = w.new_face(lat, w.F32), w.new_face(lat, w.F32)
+    gf, gb = w.new_face(lat, w.F32), w.new_face(lat, w.F32)
+    w.wd_halo_pack(g.handle, w.ODD, 0, w.F32, fin.data_ptr(), gf.data_ptr(), gb.data_ptr())
+    w.wd_autotune_dslash(g.handle, w.F32, 1, None)
+    pack_us, _ = timed_repeats(lambda: w.wd_halo_pack(g.handle, w.ODD, 0, w.F32, fin.data_ptr(), ff.data_ptr(),
+                                                      fb.data_ptr()), stream, torch)
+    halo_us, _ = timed_repeats(lambda: w.wd_dslash_halo(g.handle, w.EVEN, 0, w.F32, fin.data_ptr(), gf.data_ptr(),
+                                                        gb.data_ptr(), 1.0, 1.0, fout.data_ptr()), stream, torch)
+    plain_us, _ = timed_repeats(lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fin.data_ptr(), fout.data_ptr()),
+                                stream, torch)
+    face = w.face_bytes(lat, w.F32)
+    g.close()
+    return {"slab": "%dx%dx%dx%d" % dims, "of": "%dx%dx%dx%d" % DIMS, "slabs": nslab, "even_sites": Vh,
+            "us_dslash_with_faces": round(halo_us, 3), "us_dslash_periodic_slab": round(plain_us, 3),
+            "us_pack_both_faces": round(pack_us, 3),
+            "gflops_with_faces": round(Vh * FLOPS_DSLASH / halo_us / 1e3, 1),
+            "face_bytes_per_direction": face, "face_bytes_full_spinor_would_be": 2 * face,
+            "modelled_transfer_us_per_direction": round(face / (link_gbs * 1e3), 2)}
 
 
 def extras(w, ctx, stream, torch, ls):
@@ -162,7 +326,7 @@ def extras(w, ctx, stream, torch, ls):
     return out
 
 
-def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245, tol=1e-10):
+def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245, tol=1e-10, mdagm_gflops=None):
     """Time to an FP64-verified 1e-10 Wilson-system residual on 32^3 x 64 (eps 0.6,
     kappa 0.1245) through the even-odd CG, per inner (sloppy) storage precision,
     the level where pure FP32 recurrences stall, and flexible GMRES on the Schur
@@ -170,14 +334,24 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
     import ctypes
     X, Y, Z, T = dims
     g = w.Gauge(ctx, dims, BC, 12)
-    g.upload(ls.gauge_field(dims, eps, ls.link_seed(3)))
+    U = ls.gauge_field(dims, eps, ls.link_seed(3))
+    g.upload(U)
     lat = w.lattice(dims, BC)
     b = ls.gaussian_complex((T, Z, Y, X, 4, 3), ls.source_seed(3), ls.STREAM_SPINOR)
     fb = w.pack(ctx, lat, w.FULL, w.F64, b)
     for p in (w.F64, w.F32, w.F16, w.BF16):
         g.prepare(p)
         w.wd_autotune_dslash(g.handle, p, 1, None)
-    out = {"lattice": list(dims), "eps": eps, "kappa": kappa, "tol": tol}
+    out = {"lattice": list(dims), "eps": eps, "kappa": kappa, "tol": tol, "plaquette": round(plaquette(U), 6)}
+    del U
+    Vh = X * Y * Z * T // 2
+
+    def rates(d, flops_per_apply):
+        # operator flops only (the BLAS is not counted), per second of the whole solve
+        gf = d["operator_applies"] * Vh * flops_per_apply / d["seconds"] / 1e9
+        d["operator_gflops"] = round(gf, 1)
+        if mdagm_gflops:
+            d["operator_gflops_over_mdagm_kernel"] = round(gf / mdagm_gflops, 3)
     runs = [("f64", w.F64, False), ("f32", w.F32, False), ("f16", w.F16, False), ("bf16", w.BF16, False),
             ("pure_f32", w.F32, True)]
     default_delta = {w.F32: 1e-3, w.F16: 1e-2, w.BF16: 3e-2}   # the library's defaults (delta < 0)
@@ -191,6 +365,8 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
                               ok=(w.WD_OK, w.WD_ENOCONV))
             secs.append(info.seconds)
         d = {k: v for k, v in info.as_dict().items() if k not in ("cycles", "fell_back")}
+        d["cond_estimate"] = round(d["lambda_max"] / d["lambda_min"], 3) if d["lambda_min"] > 0 else None
+        rates(d, 2 * (2 * FLOPS_DSLASH + FLOPS_XPAY))
         d["seconds"] = round(d["seconds"], 5)
         d["seconds_first"] = round(secs[0], 5)
         d["delta"] = None if (pure or p == w.F64) else default_delta[p]
@@ -205,7 +381,8 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
             w.wd_bicgstab_solve(g.handle, kappa, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
                                 ok=(w.WD_OK, w.WD_ENOCONV))
             secs.append(info.seconds)
-        d = {k: v for k, v in info.as_dict().items() if k not in ("cycles", "fell_back")}
+        d = {k: v for k, v in info.as_dict().items() if k not in ("cycles", "fell_back", "lambda_min", "lambda_max")}
+        rates(d, 2 * FLOPS_DSLASH + FLOPS_XPAY)
         d["seconds"] = round(d["seconds"], 5)
         d["seconds_first"] = round(secs[0], 5)
         out[name] = d
@@ -225,7 +402,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
             w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), 16, nl, wid if nl else None, ptrs if nl else None,
                               net.wprec, fb.data_ptr(), fx.data_ptr(), ctypes.byref(info), ok=(w.WD_OK, w.WD_ENOCONV))
             secs.append(info.seconds)
-        d = info.as_dict()
+        d = {k: v for k, v in info.as_dict().items() if k not in ("lambda_min", "lambda_max")}
         d["seconds"] = round(d["seconds"], 5)
         d["seconds_first"] = round(secs[0], 5)
         d["restart"], d["delta"] = 16, 1e-4
@@ -267,6 +444,7 @@ def learned_extras(w, ctx):
     four gauge fields unseen in training: plain FP32 CG (with FP64 reliable updates), flexible
     GMRES without and with the committed trained network (bf16 weights on the matrix cores)."""
     import numpy as np
+    import lattice_synth as ls
     from paper_0810_5365_amd import learn
     net = learn.load_net(learn.DEFAULT_WEIGHTS, w.BF16)
     dims, kappa = (16, 16, 16, 32), 0.1248
@@ -275,12 +453,17 @@ def learned_extras(w, ctx):
         f = learn.Field(ctx, dims, 0.7, seed)
         learn.solve_compare(net, f, kappa)          # first call: packing, tuning-free warm-up
         r = learn.solve_compare(net, f, kappa)
-        rows.append({k: {kk: v[kk] for kk in ("iters", "wall_s", "true_resid_M", "fell_back")}
-                     for k, v in r.items() if isinstance(v, dict)})
+        row = {k: {kk: v[kk] for kk in ("iters", "wall_s", "true_resid_M", "fell_back")}
+               for k, v in r.items() if isinstance(v, dict)}
+        cg = r["plain_cg_f32"]
+        row["field"] = {"seed": seed, "plaquette": round(plaquette(ls.gauge_field(dims, 0.7, seed)), 6),
+                        "lambda_min_mdagm": cg["lambda_min"], "lambda_max_mdagm": cg["lambda_max"],
+                        "cond_mdagm": round(cg["lambda_max"] / cg["lambda_min"], 3) if cg["lambda_min"] > 0 else None}
+        rows.append(row)
         f.close()
     out = {"lattice": list(dims), "eps": 0.7, "kappa": kappa, "tol": 1e-10, "fields": [6001, 6002, 6003, 6004],
            "weights": "paper_0810_5365_amd/data/" + __import__("os").path.basename(learn.DEFAULT_WEIGHTS), "per_field": rows}
-    for k in rows[0]:
+    for k in (k for k in rows[0] if k != "field"):
         out["mean_" + k] = {"iters": float(np.mean([r[k]["iters"] for r in rows])),
                             "wall_ms": round(1e3 * float(np.mean([r[k]["wall_s"] for r in rows])), 3)}
     out["learned_speedup_vs_plain_cg"] = round(out["mean_plain_cg_f32"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
@@ -360,7 +543,10 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     eo_us = e0.elapsed_time(e1) * 1e3 / n_eo
-    eo = {"us_per_launch": round(eo_us, 3), "gflops": round(Vh * FLOPS_DSLASH / eo_us / 1e3, 1),
+    eo_med, eo_min = timed_repeats(lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fodd.data_ptr(), fout.data_ptr()),
+                                   stream, torch)
+    eo = {"us_per_launch": round(eo_us, 3), "us_median_5x100": round(eo_med, 3), "us_min_5x100": round(eo_min, 3),
+          "gflops": round(Vh * FLOPS_DSLASH / eo_us / 1e3, 1),
           "gbs_algorithmic": round(Vh * BYTES_DSLASH / eo_us / 1e3, 1),
           "frac_hbm": round(Vh * BYTES_DSLASH / eo_us / 1e3 / HBM_PEAK_GBS, 4),
           "gbs_naive_no_reuse": round(Vh * (8 * (48 + 96) + 96) / eo_us / 1e3, 1)}
@@ -441,9 +627,14 @@ def main():
         print("bench: multi-rhs and ragged-batch measurements", file=sys.stderr, flush=True)
         rec["extras"] = extras(w, ctx, stream, torch, ls)
         print("bench: 32^3x64 solves", file=sys.stderr, flush=True)
-        rec["solve_32c64"] = solve_extras(w, ctx, torch, ls)
+        rec["solve_32c64"] = solve_extras(w, ctx, torch, ls, mdagm_gflops=gflops)
         print("bench: learned vs plain solves on 16^3x32", file=sys.stderr, flush=True)
         rec["solve_learned_16c32"] = learned_extras(w, ctx)
+    if not args.no_extras and not args.no_sweep and dims == DIMS:
+        print("bench: volume sweep L^3 x 2L", file=sys.stderr, flush=True)
+        rec["volume_sweep"] = volume_sweep(w, ctx, stream, torch, ls, U)
+        print("bench: one t-slab of eight with half-spinor faces", file=sys.stderr, flush=True)
+        rec["slab_32c8_of_32c64"] = slab_extras(w, ctx, stream, torch, ls, U)
     if not args.no_cpu:
         print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(U, psi_e, dims)

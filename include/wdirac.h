@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 1
+#define WD_ABI_VERSION 2
 
 typedef enum {
     WD_OK = 0,
@@ -161,6 +161,38 @@ wd_status wd_apply_M(wd_gauge g, double kappa, wd_subset subset, int dagger, wd_
 wd_status wd_apply_MdagM(wd_gauge g, double kappa, wd_subset subset, wd_prec prec, int nrhs,
                          const void* in, void* out);
 
+/* ---- one device's slab of a lattice split along t (paper, Section 4: spin
+ *      projection before the colour multiply halves what crosses a face) ------
+ * The gauge object holds the slab's own sites, dims (X, Y, Z, T_local), with
+ * its links U_mu(x); a slab's first global time slice must be even, so that
+ * local and global parities agree.  Spatial hops wrap inside the slab; the
+ * t-hops that leave it use half spinors exchanged with the neighbouring slabs
+ * (by the caller: a device copy here, a transfer between devices in general).
+ * Face buffer (device, caller-owned): 12 reals per face site, X Y Z / 2 sites,
+ * as 3 planes of float4 (F32) or 6 planes of double2 (F64), plane k holding
+ * reals 4k..4k+3 (2k, 2k+1) of every site in checkerboard order of the slice. */
+/* Bytes of one face buffer (0 on bad input or a precision other than F32/F64). */
+size_t wd_face_bytes(const wd_lattice* lat, wd_prec prec);
+/* From the half field `in` of parity in_subset (EVEN or ODD) at prec (F32 or
+ * F64), fill face_fwd with (1 - s gamma_t) in on the first time slice (for the
+ * forward t-hops of the previous slab's last slice) and face_bwd with
+ * U_t(x)^dagger (1 + s gamma_t) in(x) on the last slice (for the backward
+ * t-hops of the next slab's first slice); s = +1 for D_hop, -1 for the dagger.
+ * Errors: WD_EINVAL (NULL pointer, bad subset, links not uploaded),
+ * WD_EUNSUPPORTED (16-bit precision, links in temporal gauge).  Asynchronous. */
+wd_status wd_halo_pack(wd_gauge g, wd_subset in_subset, int dagger, wd_prec prec, const void* in,
+                       void* face_fwd, void* face_bwd);
+/* out (parity out_subset) = D_hop in (the dagger if dagger != 0) on the slab,
+ * with the forward t-hops of the last slice taken from ghost_fwd (the next
+ * slab's face_fwd of its input, times sign_fwd) and the backward t-hops of the
+ * first slice from ghost_bwd (the previous slab's face_bwd, times sign_bwd).
+ * The signs are the t boundary condition where the hop crosses the global t
+ * edge, else +1.  in: half field of the other parity; out must not alias it.
+ * Errors as wd_halo_pack.  Asynchronous. */
+wd_status wd_dslash_halo(wd_gauge g, wd_subset out_subset, int dagger, wd_prec prec, const void* in,
+                         const void* ghost_fwd, const void* ghost_bwd, double sign_fwd, double sign_bwd,
+                         void* out);
+
 /* ---- global sums in float64 (paper, Section 4) ---------------------------- */
 /* result[0] + i result[1] = <a, b> = sum conj(a_i) b_i over the whole field
  * (all rhs).  Deterministic: fixed-order two-pass reduction.  Synchronous. */
@@ -195,6 +227,12 @@ typedef struct {
     double seconds;         /* wall time from call to return                      */
     int cycles;             /* flexible GMRES: restart cycles (float64 residual updates) */
     int fell_back;          /* flexible GMRES: 1 if it handed over to the plain CG      */
+    double lambda_min;      /* CG: smallest and largest Ritz value of the solved operator */
+    double lambda_max;      /* (A = M^dag M or Mhat^dag Mhat) from the CG step lengths and
+                               residual ratios (the Lanczos tridiagonal); estimates of the
+                               ends of its spectrum, lambda_min from above, lambda_max
+                               from below.  0 where not computed (other solvers, a
+                               breakdown, or no iteration).                           */
 } wd_solver_info;
 
 /* Solve A x = b, A = M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD), by CG.

@@ -91,6 +91,8 @@ static wd_status finish(wd_context ctx, int nblk, int n, bool fetch, int slot = 
     return WD_OK;
 }
 
+wd_status reduce_partials(wd_context ctx, int nblk, int slot) { return finish(ctx, nblk, 1, false, slot); }
+
 wd_status fetch_results(wd_context ctx, int n)
 {
     if (!ctx->hres_dev)   // no mapped host buffer: copy the results over

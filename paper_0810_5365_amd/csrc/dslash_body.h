@@ -41,6 +41,7 @@ struct DslashArgs {
     int zb;          // > 0: z-blocked site traversal with this block depth (divides Z)
     int gf;          // links in temporal gauge: U_t = 1 except on the last time slice
     FastDiv dzb, dt; // division by zb and by T for the blocked traversal
+    double* nrm;     // per-workgroup partial sums of |out|^2 (the kernels that fuse the norm)
 };
 
 // Site order index i -> checkerboard index and coordinates of the z-blocked
@@ -139,8 +140,11 @@ __device__ __forceinline__ void hop_pipelined(const DslashArgs& A, uint32_t cb, 
     order_fence(acc);
 }
 
-template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
-__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, const int c[4], int rhs)
+// With NRM, *nrm receives the site's sum of squares of the result (in float64, from the
+// values before they are rounded to the storage precision).
+template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, bool NRM = false>
+__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, const int c[4], int rhs,
+                                            double* nrm = nullptr)
 {
     using T = typename RealOf<P>::T;
     const size_t gbytes = link_site_bytes(P, R) * (size_t)A.g.ps;
@@ -180,15 +184,21 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= b;
     }
+    if constexpr (NRM) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) s += (double)acc[k] * (double)acc[k];
+        *nrm = s;
+    }
     SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.ps, cb, acc);
 }
 
-template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
-__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs)
+template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, bool NRM = false>
+__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs, double* nrm = nullptr)
 {
     int c[4];
     cb_coords(A.g, cb, A.par, c);
-    dslash_site<P, R, DAG, XPAY, NT, PF>(A, cb, c, rhs);
+    dslash_site<P, R, DAG, XPAY, NT, PF, NRM>(A, cb, c, rhs, nrm);
 }
 
 } // namespace wd

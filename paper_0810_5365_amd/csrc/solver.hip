@@ -5,12 +5,63 @@
 // accumulated in float64 through reliable updates, each of which recomputes
 // the true residual b - A x in float64 (Sleijpen and van der Vorst's
 // reliable-update scheme).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <vector>
 
 #include "wd_ops.h"
 
 namespace wd {
+
+// Number of eigenvalues below x of the symmetric tridiagonal matrix with diagonal
+// d[0..n) and off-diagonal e[0..n-1), by the signs of the pivots of T - x
+// (Sturm sequence count).
+static int sturm_count(const std::vector<double>& d, const std::vector<double>& e, double x)
+{
+    int neg = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < d.size(); i++) {
+        q = d[i] - x - (i ? e[i - 1] * e[i - 1] / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) neg++;
+    }
+    return neg;
+}
+
+// Extreme eigenvalues of the Lanczos tridiagonal that CG builds implicitly from its
+// step lengths alpha_j and ratios beta_j = |r_{j+1}|^2 / |r_j|^2: diagonal
+// 1/alpha_j + beta_{j-1}/alpha_{j-1}, off-diagonal sqrt(beta_j)/alpha_j.  Their
+// eigenvalues (Ritz values) approach the ends of the spectrum of the solved operator
+// as the iteration proceeds.  Bisection on the Sturm count to relative 1e-13.
+static void cg_ritz_extremes(const std::vector<double>& alpha, const std::vector<double>& beta, double* lo,
+                             double* hi)
+{
+    const size_t n = alpha.size();
+    *lo = *hi = 0.0;
+    if (n == 0) return;
+    std::vector<double> d(n), e(n > 1 ? n - 1 : 0);
+    for (size_t j = 0; j < n; j++) {
+        d[j] = 1.0 / alpha[j] + (j ? beta[j - 1] / alpha[j - 1] : 0.0);
+        if (j + 1 < n) e[j] = std::sqrt(beta[j]) / alpha[j];
+    }
+    double a = d[0], b = d[0];   // Gershgorin interval
+    for (size_t j = 0; j < n; j++) {
+        const double r = (j ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < n ? std::fabs(e[j]) : 0.0);
+        a = std::min(a, d[j] - r);
+        b = std::max(b, d[j] + r);
+    }
+    auto kth = [&](int k) {   // the (k+1)-th smallest eigenvalue
+        double l = a, u = b;
+        for (int it = 0; it < 200 && u - l > 1e-13 * std::max(std::fabs(l), std::fabs(u)); it++) {
+            const double m = 0.5 * (l + u);
+            if (sturm_count(d, e, m) > k) u = m; else l = m;
+        }
+        return 0.5 * (l + u);
+    };
+    *lo = kth(0);
+    *hi = kth((int)n - 1);
+}
 
 struct CGProblem {
     wd_gauge g;
@@ -56,21 +107,21 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     const double delta = resolve_delta(prm.delta, pop);
     const bool use_delta = pop != WD_F64 && delta > 0.0;
 
-    void *r, *rs, *xs, *p, *ap;
+    void *r, *rs, *xs, *p, *ap, *mp;
     WD_TRY(ws_get(ctx, "cg.r", half_bytes(G, WD_F64) * nh, &r));
     WD_TRY(ws_get(ctx, "cg.rs", half_bytes(G, pacc) * nh, &rs));
     WD_TRY(ws_get(ctx, "cg.xs", half_bytes(G, pacc) * nh, &xs));
     WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &p));
     WD_TRY(ws_get(ctx, "cg.ap", half_bytes(G, pop) * nh, &ap));
+    WD_TRY(ws_get(ctx, "cg.mp", half_bytes(G, pop) * nh, &mp));
 
     WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
     const double cc = ctx->hres[0];
     const double tol2 = prm.tol * prm.tol;
     const double target_r = tol2 * cc;
     const double target_w = tol2 * P.wnorm2;
-    info->iters = 0;
-    info->reliable_updates = 0;
-    info->operator_applies = 0;
+    *info = wd_solver_info{};
+    std::vector<double> alphas, betas;   // for the Ritz-value estimates
     if (!(cc > 0.0)) {
         WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
         info->true_resid = 0.0;
@@ -95,9 +146,11 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
         WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
         double rr_s = rr, maxrr = rr;
         while (info->iters < prm.maxiter) {
-            WD_TRY(op_MdagM(P.g, P.kappa, P.subset, pop, 1, p, ap));
+            // A p = M^dag (M p), and <p, A p> = ||M p||^2 summed by the kernel that writes M p
+            WD_TRY(op_M_norm(P.g, P.kappa, P.subset, pop, p, mp, 0));
+            WD_TRY(op_M(P.g, P.kappa, P.subset, 1, pop, 1, mp, ap));
+            WD_TRY(fetch_results(ctx, 1));
             info->operator_applies++;
-            WD_TRY(blas_dot(ctx, G, nh, pop, p, ap, true));
             const double pap = ctx->hres[0];
             if (!std::isfinite(pap) || !(pap > 0.0)) {
                 set_error("CG breakdown: <p, A p> = %g at iteration %d", pap, info->iters);
@@ -105,6 +158,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
                 break;
             }
             const double alpha = rr_s / pap;
+            alphas.push_back(alpha);
             WD_TRY(blas_cg_xr(ctx, G, nh, pacc, xs, rs, pop, p, ap, alpha, true));
             xs_dirty = true;
             double rr_new = ctx->hres[0];
@@ -135,6 +189,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
             }
             if (rr_new > maxrr) maxrr = rr_new;
             const double beta = rr_new / rr_s;
+            betas.push_back(beta);
             WD_TRY(blas_cg_p(ctx, G, nh, pacc, rs, pop, p, beta));
             rr_s = rr_new;
         }
@@ -146,6 +201,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     }
     info->true_resid = std::sqrt(rr / cc);
     info->true_resid_M = P.bhat ? std::sqrt(ww / P.wnorm2) : -1.0;
+    if (status != WD_ENAN) cg_ritz_extremes(alphas, betas, &info->lambda_min, &info->lambda_max);
     if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
     if (status == WD_ENOCONV)
         set_error("CG did not reach tol %g in %d iterations (residual %g)", prm.tol, info->iters,

@@ -120,6 +120,11 @@ struct DslashCall {
 };
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
+wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp, double* nrm,
+                              int* nblocks);
+// The same launch with |out|^2 summed per workgroup into partials[0 .. *nblocks)
+// (the caller sizes partials for one sum per workgroup of 64 sites and rhs).
+wd_status launch_dslash_norm(wd_context ctx, const Geom& g, const DslashCall& c, double* partials, int* nblocks);
 // ---- dslash_mrhs.hip: 16 rhs per wave with the colour multiply on the matrix cores ----
 bool mrhs_eligible(const DslashCall& c);
 wd_status launch_dslash_mrhs(wd_context ctx, const Geom& g, const DslashCall& c);
@@ -150,6 +155,8 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
+// dres[slot] (and hres) = the sum of partials[0 .. nblk), in a fixed order; not fetched
+wd_status reduce_partials(wd_context ctx, int nblk, int slot);
 // out = sum_{i < n} (cre[i] + i cim[i]) x[i], n <= 3, out may alias an input; with r0 non-null also
 // ||out||^2 and <r0, out> (dres/hres 0; 1, 2)
 wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nhalves, int prec, int n, const void* const* x,

@@ -13,6 +13,9 @@ wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, cons
                     double a, double b);
 // M (FULL) or Mhat (EVEN / ODD), or their daggers
 wd_status op_M(wd_gauge g, double kappa, int subset, int dagger, int prec, int nrhs, const void* in, void* out);
+// out = M in (FULL) or Mhat in (EVEN / ODD), one rhs, with ||out||^2 summed in the last
+// launch into dres[slot] and hres[slot] (not fetched: synchronise before reading hres)
+wd_status op_M_norm(wd_gauge g, double kappa, int subset, int prec, const void* in, void* out, int slot);
 // M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD)
 wd_status op_MdagM(wd_gauge g, double kappa, int subset, int prec, int nrhs, const void* in, void* out);
 

@@ -39,7 +39,8 @@ class WdSolverParams(ctypes.Structure):
 class WdSolverInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("operator_applies", ctypes.c_int),
                 ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("true_resid_M", ctypes.c_double),
-                ("seconds", ctypes.c_double), ("cycles", ctypes.c_int), ("fell_back", ctypes.c_int)]
+                ("seconds", ctypes.c_double), ("cycles", ctypes.c_int), ("fell_back", ctypes.c_int),
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -105,9 +106,13 @@ _PROTOS = {
     "wd_tune_load": ("status", [_V, ctypes.c_char_p]),
     "wd_tune_get": (_I, [_V, ctypes.c_char_p, _P(_I)]),
     "wd_tune_get_n": (_I, [_V, ctypes.c_char_p, _P(_I), _I]),
+    "wd_face_bytes": (_S, [_P(WdLattice), _I]),
+    "wd_halo_pack": ("status", [_V, _I, _I, _I, _V, _V, _V]),
+    "wd_dslash_halo": ("status", [_V, _I, _I, _I, _V, _V, _V, _D, _D, _V]),
 }
 
 _lib = None
+ABI_VERSION = 2   # the structures above match include/wdirac.h at this version
 
 
 def _raw():
@@ -121,6 +126,9 @@ def _raw():
             f = getattr(lib, name)
             f.restype = _I if res == "status" else res
             f.argtypes = args
+        if lib.wd_abi_version() != ABI_VERSION:
+            raise ImportError("%s has ABI version %d, this binding expects %d; rebuild it"
+                              % (LIB_PATH, lib.wd_abi_version(), ABI_VERSION))
         _lib = lib
     return _lib
 
@@ -241,6 +249,19 @@ def new_field(lat, subset, prec, nrhs=1, device=0):
     n = spinor_bytes(lat, subset, prec, nrhs)
     if n == 0:
         raise ValueError("bad field description")
+    return torch.empty(n, dtype=torch.uint8, device="cuda:%d" % device)
+
+
+def face_bytes(lat, prec):
+    return int(wd_face_bytes(ctypes.byref(lat), int(prec)))
+
+
+def new_face(lat, prec, device=0):
+    """An uninitialised face buffer of a t-slab (torch uint8 tensor)."""
+    import torch
+    n = face_bytes(lat, prec)
+    if n == 0:
+        raise ValueError("bad face description")
     return torch.empty(n, dtype=torch.uint8, device="cuda:%d" % device)
 
 

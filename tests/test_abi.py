@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(w):
 
 
 def test_abi_version_and_status_strings(w):
-    assert w.wd_abi_version() == 1
+    assert w.wd_abi_version() == w.ABI_VERSION == 2
     for s in range(8):
         assert w.wd_status_string(s).startswith(b"WD_")
     assert b"unknown" in w.wd_status_string(99)
@@ -73,6 +73,14 @@ def test_spinor_bytes(w):
     assert w.spinor_bytes(lat, w.EVEN, 9) == 0
     assert w.spinor_bytes(lat, w.EVEN, w.F32, 0) == 0
     assert w.spinor_bytes(w.lattice((8, 8, 8, 16), bc=(1, 1, 1, 3)), w.EVEN, w.F32) == 0
+
+
+def test_face_bytes(w):
+    """A t-slab face: X Y Z / 2 sites of 12 reals (48 B in F32, 96 B in F64), unpadded."""
+    assert w.face_bytes(w.lattice((32, 32, 32, 8)), w.F32) == 32 ** 3 // 2 * 48
+    assert w.face_bytes(w.lattice((4, 6, 2, 8)), w.F64) == 24 * 96
+    assert w.face_bytes(w.lattice((4, 6, 2, 8)), w.F16) == 0
+    assert w.face_bytes(w.lattice((7, 6, 2, 8)), w.F32) == 0
 
 
 def test_null_arguments_return_einval(w):

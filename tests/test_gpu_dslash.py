@@ -345,6 +345,65 @@ def test_cg_maxiter_reports_noconv(w, ctx):
     assert info.iters == 2 and 0 < info.true_resid < 1
 
 
+def _dense_mdagm_spectrum(U, dims, kappa):
+    """Eigenvalues of the oracle's Mhat^dag Mhat as a dense matrix (unit vectors in)."""
+    n = dims[0] * dims[1] * dims[2] * dims[3] // 2 * 12
+    A = np.empty((n, n), complex)
+    for i in range(n):
+        e = np.zeros(n, complex)
+        e[i] = 1.0
+        A[:, i] = orc.mhat_dag_mhat(U, e.reshape(-1, 4, 3), kappa, BC).reshape(-1)
+    return np.linalg.eigvalsh(A)
+
+
+@pytest.mark.parametrize("sloppy,solver", [("f64", "cg"), ("f32", "cg"), ("f32", "wilson")])
+def test_cg_ritz_values_match_the_spectrum_ends(w, ctx, sloppy, solver):
+    """The extreme Ritz values the CG reports (from its step lengths and residual ratios)
+    against the ends of the spectrum of the oracle's dense Mhat^dag Mhat on 4^4: inside
+    the spectrum, and within 1% of its ends once the solve has converged."""
+    dims, kappa = (4, 4, 4, 4), 0.124
+    U, g = gauge(w, ctx, dims, 0.3, 3003, 12)
+    ev = _dense_mdagm_spectrum(U, dims, kappa)
+    lat = w.lattice(dims, BC)
+    sub = w.EVEN if solver == "cg" else w.FULL
+    c = source(w, dims, sub, 35)
+    fb = w.pack(ctx, lat, sub, w.F64, c)
+    fx = w.pack(ctx, lat, sub, w.F64, np.zeros_like(c))
+    prm = w.solver_params(tol=1e-12, maxiter=2000, sloppy=w.PREC_BY_NAME[sloppy])
+    info = w.WdSolverInfo()
+    if solver == "cg":
+        w.wd_cg_solve(g.handle, kappa, w.EVEN, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info))
+    else:
+        w.wd_wilson_solve(g.handle, kappa, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info))
+    assert info.status == w.WD_OK
+    # a lattice spectrum is dense at both ends, so the extreme Ritz values approach them
+    # slowly (1e-3 after the 40 iterations to 1e-12 here); the float32 iterations perturb
+    # the coefficients, which may move them slightly outside
+    out = 1e-9 if sloppy == "f64" else 1e-4
+    lo, hi = info.lambda_min, info.lambda_max
+    assert ev[0] * (1 - out) <= lo <= ev[0] * (1 + 1e-2), (lo, ev[0], info.as_dict())
+    assert ev[-1] * (1 - 1e-2) <= hi <= ev[-1] * (1 + out), (hi, ev[-1], info.as_dict())
+
+
+def test_cg_ritz_values_of_a_short_run_lie_inside(w, ctx):
+    """Two iterations: the Ritz values of the 2x2 tridiagonal are inside the spectrum
+    (Cauchy interlacing) but not yet at its ends."""
+    dims, kappa = (4, 4, 4, 4), 0.124
+    U, g = gauge(w, ctx, dims, 0.3, 3003, 12)
+    ev = _dense_mdagm_spectrum(U, dims, kappa)
+    lat = w.lattice(dims, BC)
+    c = source(w, dims, w.EVEN, 36)
+    fb = w.pack(ctx, lat, w.EVEN, w.F64, c)
+    fx = w.pack(ctx, lat, w.EVEN, w.F64, np.zeros_like(c))
+    prm = w.solver_params(tol=1e-12, maxiter=2, sloppy=w.F64)
+    info = w.WdSolverInfo()
+    w.wd_cg_solve(g.handle, kappa, w.EVEN, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info),
+                  ok=(w.WD_OK, w.WD_ENOCONV))
+    assert info.iters == 2
+    assert ev[0] < info.lambda_min < info.lambda_max < ev[-1], (info.as_dict(), ev[0], ev[-1])
+    assert info.lambda_min > ev[0] * 1.01
+
+
 def test_bad_arguments_leave_outputs_untouched(w, ctx):
     dims = (4, 4, 4, 4)
     U, g = gauge(w, ctx, dims, 0.5, 5, 12)
