@@ -45,7 +45,13 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         return WD_OK;
     };
     double rr;
-    WD_TRY(true_res(&rr));
+    if (is_zero_f64(ctx, G, 1, x)) {   // zero guess: r = bhat without the operator
+        WD_TRY(launch_convert(ctx, G, 1, WD_F64, bhat, WD_F64, r));
+        WD_TRY(blas_norm2(ctx, G, 1, WD_F64, bhat, true));
+        rr = ctx->hres[0];
+    } else {
+        WD_TRY(true_res(&rr));
+    }
     WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, rs));
     WD_TRY(launch_convert(ctx, G, 1, WD_F64, r, ps, r0));
     WD_TRY(blas_zero(ctx, G, 1, ps, p));
@@ -56,8 +62,9 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     bool dirty = false;
     wd_status status = WD_ENOCONV;
     if (rr <= target) status = WD_OK;
-    // Each iteration: 2 operator applications and 5 fused sweeps, 3 of them reductions the host
-    // waits for (<r0, v>; <t, s> with ||t||^2; ||r||^2 with <r0, r> from the r update itself).
+    // Each iteration: 2 operator applications, whose last launches also sum <r0, v> and
+    // <t, s> with ||t||^2, and 4 fused vector sweeps, the last with ||r||^2 and <r0, r> (the
+    // next rho); the host waits three times.
     cd rho_new;
     bool have_rho = false;
     while (status != WD_OK && info->iters < prm.maxiter) {
@@ -74,18 +81,20 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
             const double cr[3] = {1.0, beta.real(), c2.real()}, ci[3] = {0.0, beta.imag(), c2.imag()};
             WD_TRY(blas_lincomb(ctx, G, 1, ps, 3, in, cr, ci, p, nullptr, false));
         }
-        WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, p, v));
-        cd r0v;
-        WD_TRY(dot(r0, v, &r0v));
+        // v = Mhat p with <r0, v> summed by the launch that writes v
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, ps, p, v, RED_YDOT, r0, 0));
+        WD_TRY(fetch_results(ctx, 2));
+        const cd r0v(ctx->hres[0], ctx->hres[1]);
         alpha = rho_new / r0v;
         {   // s = r - alpha v
             const void* in[2] = {rs, v};
             const double cr[2] = {1.0, -alpha.real()}, ci[2] = {0.0, -alpha.imag()};
             WD_TRY(blas_lincomb(ctx, G, 1, ps, 2, in, cr, ci, s, nullptr, false));
         }
-        WD_TRY(op_M(g, kappa, WD_EVEN, 0, ps, 1, s, t));
+        // t = Mhat s with <t, s> and ||t||^2 summed by the launch that writes t (s is its a x term)
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, ps, s, t, RED_XDOT, nullptr, 0));
+        WD_TRY(fetch_results(ctx, 3));
         info->operator_applies += 2;
-        WD_TRY(blas_dot_norm(ctx, G, 1, ps, t, s, true));
         const cd ts(ctx->hres[0], ctx->hres[1]);
         const double tt = ctx->hres[2];
         omega = tt > 0.0 ? ts / tt : cd(0.0);

@@ -91,7 +91,12 @@ static wd_status finish(wd_context ctx, int nblk, int n, bool fetch, int slot = 
     return WD_OK;
 }
 
-wd_status reduce_partials(wd_context ctx, int nblk, int slot) { return finish(ctx, nblk, 1, false, slot); }
+bool is_zero_f64(wd_context ctx, const Geom& g, size_t nhalves, const void* x)
+{
+    return blas_norm2(ctx, g, nhalves, WD_F64, x, true) == WD_OK && ctx->hres[0] == 0.0;
+}
+
+wd_status reduce_partials(wd_context ctx, int nblk, int n, int slot) { return finish(ctx, nblk, n, false, slot); }
 
 wd_status fetch_results(wd_context ctx, int n)
 {

@@ -27,73 +27,23 @@ __global__ void __launch_bounds__(256) dslash_kernel(DslashArgs A)
     }
 }
 
-// The same with the result's |out|^2 summed per workgroup into A.nrm[workgroup]
-// (every work-item takes part in the sum, those past the last site with 0).
 template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
-__global__ void __launch_bounds__(256) dslash_norm_kernel(DslashArgs A)
-{
-    uint32_t bid = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-    int rhs = blockIdx.y;
-    if (A.rhs_inner > 1) {
-        rhs = (int)(bid % (uint32_t)A.rhs_inner);
-        bid /= (uint32_t)A.rhs_inner;
-    }
-    const uint32_t i = bid * blockDim.x + threadIdx.x;
-    double s = 0.0;
-    if (i < (uint32_t)A.g.Vh) {
-        if (A.zb > 0) {
-            int c[4];
-            const uint32_t cb = zblock_site(A, i, c);
-            dslash_site<P, R, DAG, XPAY, NT, PF, true>(A, cb, c, rhs, &s);
-        } else {
-            dslash_site<P, R, DAG, XPAY, NT, PF, true>(A, i, rhs, &s);
-        }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    __shared__ double lds[4];
-    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (uint32_t w = 0; w < blockDim.x / 64; ++w) t += lds[w];
-        A.nrm[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
-    }
-}
-
-template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF>
-static wd_status run(wd_context ctx, const DslashArgs& A, int nrhs, const TuneParam& tp, int* nblocks)
+static wd_status run(wd_context ctx, const DslashArgs& A, int nrhs, const TuneParam& tp)
 {
     dim3 block(tp.block);
     const unsigned nblk = (A.g.Vh + tp.block - 1) / tp.block;
     dim3 grid = A.rhs_inner > 1 ? dim3(nblk * (unsigned)nrhs, 1) : dim3(nblk, nrhs);
-    if (A.nrm) {
-        if constexpr (XPAY && !DAG) {   // the only form the solvers fuse: ||x - kappa^2 D in||^2
-            if ((size_t)grid.x * grid.y > ctx->npartials) {
-                set_error("dslash: %u workgroup sums do not fit the %zu reduction slots", grid.x * grid.y,
-                          ctx->npartials);
-                return WD_EINVAL;
-            }
-            hipLaunchKernelGGL((dslash_norm_kernel<P, R, DAG, XPAY, NT, PF>), grid, block, 0, ctx->stream, A);
-            *nblocks = (int)(grid.x * grid.y);
-        } else {
-            set_error("dslash: the fused norm is built for a x + b D in without the dagger only");
-            return WD_EUNSUPPORTED;
-        }
-    } else {
-        hipLaunchKernelGGL((dslash_kernel<P, R, DAG, XPAY, NT, PF>), grid, block, 0, ctx->stream, A);
-    }
+    hipLaunchKernelGGL((dslash_kernel<P, R, DAG, XPAY, NT, PF>), grid, block, 0, ctx->stream, A);
     WD_LAUNCHED();
     return WD_OK;
 }
 
 template <int P, int R>
-static wd_status dispatch_pr(wd_context ctx, const DslashArgs& A, const DslashCall& c, const TuneParam& tp,
-                             int* nblocks)
+static wd_status dispatch_pr(wd_context ctx, const DslashArgs& A, const DslashCall& c, const TuneParam& tp)
 {
     const int sel = (c.dagger ? 1 : 0) | (c.x ? 2 : 0) | (tp.nt ? 4 : 0) | (tp.pf ? 8 : 0);
     switch (sel) {
-#define WD_DS(K) case K: return run<P, R, (K & 1) != 0, (K & 2) != 0, (K & 4) != 0, (K & 8) != 0>(ctx, A, c.nrhs, tp, nblocks);
+#define WD_DS(K) case K: return run<P, R, (K & 1) != 0, (K & 2) != 0, (K & 4) != 0, (K & 8) != 0>(ctx, A, c.nrhs, tp);
     WD_DS(0) WD_DS(1) WD_DS(2) WD_DS(3) WD_DS(4) WD_DS(5) WD_DS(6) WD_DS(7)
     WD_DS(8) WD_DS(9) WD_DS(10) WD_DS(11) WD_DS(12) WD_DS(13) WD_DS(14) WD_DS(15)
 #undef WD_DS
@@ -101,20 +51,13 @@ static wd_status dispatch_pr(wd_context ctx, const DslashArgs& A, const DslashCa
     return WD_EINVAL;
 }
 
-wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp)
+wd_status dslash_setup(const Geom& g, const DslashCall& c, const TuneParam& tp, DslashArgs* out)
 {
-    return launch_dslash_tuned(ctx, g, c, tp, nullptr, nullptr);
-}
-
-wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp, double* nrm,
-                              int* nblocks)
-{
-    if (tp.mf && mrhs_eligible(c) && !nrm) return launch_dslash_mrhs(ctx, g, c);
     if (tp.block <= 0 || tp.block > 256 || tp.block % 64) {
         set_error("dslash: workgroup size %d not in {64, 128, 192, 256}", tp.block);
         return WD_EINVAL;
     }
-    DslashArgs A;
+    DslashArgs A{};
     A.gauge = (const char*)c.gauge;
     A.in = (const char*)c.in;
     A.out = (char*)c.out;
@@ -129,7 +72,6 @@ wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c
     A.remap = tp.remap;
     A.rhs_inner = (tp.rhs_inner && c.nrhs > 1) ? c.nrhs : 0;
     A.gf = c.gf;
-    A.nrm = nrm;
     A.zb = 0;
     if (tp.zb > 0 && tp.zb < g.L[2] && g.L[2] % tp.zb == 0) {
         A.zb = tp.zb;
@@ -137,17 +79,26 @@ wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c
         A.dt = make_fastdiv((uint32_t)g.L[3]);
     }
     if ((long long)((g.Vh + tp.block - 1) / tp.block) * c.nrhs >= (1ll << 31)) A.rhs_inner = 0;
+    *out = A;
+    return WD_OK;
+}
+
+wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp)
+{
+    if (tp.mf && mrhs_eligible(c)) return launch_dslash_mrhs(ctx, g, c);
+    DslashArgs A;
+    WD_TRY(dslash_setup(g, c, tp, &A));
     const bool r12 = c.recon == 12;
     switch (c.prec) {
-    case WD_F64: return r12 ? dispatch_pr<P_F64, 12>(ctx, A, c, tp, nblocks) : dispatch_pr<P_F64, 18>(ctx, A, c, tp, nblocks);
-    case WD_F32: return r12 ? dispatch_pr<P_F32, 12>(ctx, A, c, tp, nblocks) : dispatch_pr<P_F32, 18>(ctx, A, c, tp, nblocks);
-    case WD_F16: return r12 ? dispatch_pr<P_F16, 12>(ctx, A, c, tp, nblocks) : dispatch_pr<P_F16, 18>(ctx, A, c, tp, nblocks);
-    case WD_BF16: return r12 ? dispatch_pr<P_BF16, 12>(ctx, A, c, tp, nblocks) : dispatch_pr<P_BF16, 18>(ctx, A, c, tp, nblocks);
+    case WD_F64: return r12 ? dispatch_pr<P_F64, 12>(ctx, A, c, tp) : dispatch_pr<P_F64, 18>(ctx, A, c, tp);
+    case WD_F32: return r12 ? dispatch_pr<P_F32, 12>(ctx, A, c, tp) : dispatch_pr<P_F32, 18>(ctx, A, c, tp);
+    case WD_F16: return r12 ? dispatch_pr<P_F16, 12>(ctx, A, c, tp) : dispatch_pr<P_F16, 18>(ctx, A, c, tp);
+    case WD_BF16: return r12 ? dispatch_pr<P_BF16, 12>(ctx, A, c, tp) : dispatch_pr<P_BF16, 18>(ctx, A, c, tp);
     default: set_error("dslash: bad precision %d", c.prec); return WD_EINVAL;
     }
 }
 
-static std::string dslash_key(const Geom& g, const DslashCall& c)
+std::string dslash_key(const Geom& g, const DslashCall& c)
 {
     char key[160];
     snprintf(key, sizeof key, "dslash:%dx%dx%dx%d:p%d:r%d:n%d:d%d:x%d", g.L[0], g.L[1], g.L[2], g.L[3], c.prec,
@@ -158,15 +109,6 @@ static std::string dslash_key(const Geom& g, const DslashCall& c)
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c)
 {
     return launch_dslash_tuned(ctx, g, c, tune_lookup(ctx, dslash_key(g, c)));
-}
-
-wd_status launch_dslash_norm(wd_context ctx, const Geom& g, const DslashCall& c, double* partials, int* nblocks)
-{
-    if (!partials || !nblocks) {
-        set_error("dslash: no reduction buffer for the fused norm");
-        return WD_EINVAL;
-    }
-    return launch_dslash_tuned(ctx, g, c, tune_lookup(ctx, dslash_key(g, c)), partials, nblocks);
 }
 
 } // namespace wd

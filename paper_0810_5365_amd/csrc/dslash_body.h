@@ -41,8 +41,46 @@ struct DslashArgs {
     int zb;          // > 0: z-blocked site traversal with this block depth (divides Z)
     int gf;          // links in temporal gauge: U_t = 1 except on the last time slice
     FastDiv dzb, dt; // division by zb and by T for the blocked traversal
-    double* nrm;     // per-workgroup partial sums of |out|^2 (the kernels that fuse the norm)
+    double* red;     // per-workgroup partial sums of a fused reduction (dslash_red.hip)
+    const char* y;   // the other operand of the fused <y, out>
 };
+
+// Kernel arguments for a launch of the hopping term with launch shape tp (dslash.hip).
+wd_status dslash_setup(const Geom& g, const DslashCall& c, const TuneParam& tp, DslashArgs* A);
+
+// v <- the values that storing v at 16-bit precision and loading it back gives (the store's
+// scale and rounding, repeated).
+template <int P> __device__ __forceinline__ void quant_roundtrip(float* v)
+{
+    float s = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) s = fmaxf(s, fabsf(v[k]));
+    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
+#pragma unroll
+    for (int k = 0; k < 24; ++k) v[k] = h2f<P>(f2h<P>(v[k] * inv)) * s;
+}
+
+// Reductions a fused-update launch (out = a x + b D in) can sum in its epilogue, per site in
+// float64 from the stored values:
+//   RED_NORM  |out|^2                        -> r[0]
+//   RED_XDOT  <out, x>, |out|^2              -> r[0] + i r[1], r[2]
+//   RED_YDOT  <y, out> (y = A.y), |out|^2    -> r[0] + i r[1], r[2]
+template <typename T>
+__device__ __forceinline__ void site_dot_norm(const T* a, const T* b, const T* o, double* r)
+{
+    double re = 0.0, im = 0.0, nn = 0.0;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
+        re += ar * br + ai * bi;
+        im += ar * bi - ai * br;
+    }
+#pragma unroll
+    for (int k = 0; k < 24; ++k) nn += (double)o[k] * (double)o[k];
+    r[0] = re;
+    r[1] = im;
+    r[2] = nn;
+}
 
 // Site order index i -> checkerboard index and coordinates of the z-blocked
 // traversal: i = xh + Xh (y + Y (zi + zb (t + T b))), z = b zb + zi.  Sites of
@@ -140,11 +178,11 @@ __device__ __forceinline__ void hop_pipelined(const DslashArgs& A, uint32_t cb, 
     order_fence(acc);
 }
 
-// With NRM, *nrm receives the site's sum of squares of the result (in float64, from the
-// values before they are rounded to the storage precision).
-template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, bool NRM = false>
+// RED > 0 (with XPAY): the site's values of that fused reduction go to red[0 .. 3).  The
+// output is stored first, so the reduction adds no registers to the store.
+template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, int RED = 0>
 __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, const int c[4], int rhs,
-                                            double* nrm = nullptr)
+                                            double* red = nullptr)
 {
     using T = typename RealOf<P>::T;
     const size_t gbytes = link_site_bytes(P, R) * (size_t)A.g.ps;
@@ -174,8 +212,8 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
         hop<7, P, R, DAG, NT>(A, cb, c, in, gbytes, acc);
     }
     const T b = (T)A.b;
+    T xv[24];
     if constexpr (XPAY) {
-        T xv[24];
         SpinorIO<P>::load(A.x + rhs * A.x_stride, A.g.ps, cb, xv);
         const T a = (T)A.a;
 #pragma unroll
@@ -184,21 +222,31 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= b;
     }
-    if constexpr (NRM) {
-        double s = 0.0;
-#pragma unroll
-        for (int k = 0; k < 24; ++k) s += (double)acc[k] * (double)acc[k];
-        *nrm = s;
-    }
     SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.ps, cb, acc);
+    if constexpr (RED > 0) {
+        // the reduction sees the values a later load returns (16-bit: the codes times the scale)
+        if constexpr (P == P_F16 || P == P_BF16) quant_roundtrip<P>(acc);
+        if constexpr (RED == 1) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) s += (double)acc[k] * (double)acc[k];
+            red[0] = s;
+        } else if constexpr (RED == 2) {
+            site_dot_norm(acc, xv, acc, red);
+        } else {
+            T yv[24];
+            SpinorIO<P>::load(A.y + rhs * A.out_stride, A.g.ps, cb, yv);
+            site_dot_norm(yv, acc, acc, red);
+        }
+    }
 }
 
-template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, bool NRM = false>
-__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs, double* nrm = nullptr)
+template <int P, int R, bool DAG, bool XPAY, bool NT, bool PF, int RED = 0>
+__device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, int rhs, double* red = nullptr)
 {
     int c[4];
     cb_coords(A.g, cb, A.par, c);
-    dslash_site<P, R, DAG, XPAY, NT, PF, NRM>(A, cb, c, rhs, nrm);
+    dslash_site<P, R, DAG, XPAY, NT, PF, RED>(A, cb, c, rhs, red);
 }
 
 } // namespace wd

@@ -127,7 +127,13 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         return WD_OK;
     };
     double rr;
-    WD_TRY(schur_res(&rr));
+    if (is_zero_f64(ctx, G, 1, x_e)) {   // zero guess: rhat = bhat without the operator
+        WD_TRY(launch_convert(ctx, G, 1, WD_F64, bhat, WD_F64, rhat));
+        WD_TRY(blas_norm2(ctx, G, 1, WD_F64, bhat, true));
+        rr = ctx->hres[0];
+    } else {
+        WD_TRY(schur_res(&rr));
+    }
     const double inner = prm.delta > 0.0 ? prm.delta : 1e-4;
     while (rr > tol2 && info->iters < prm.maxiter) {
         // ---- one float32 cycle on Mhat e_e = rhat_e --------------------------------

@@ -131,8 +131,18 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     }
 
     double rr, ww;
-    WD_TRY(true_residual(P, x, r, &rr, &ww));
-    info->operator_applies++;
+    if (is_zero_f64(ctx, G, nh, x)) {   // zero guess: r = c and bhat - Mhat x = bhat, without the operator
+        WD_TRY(launch_convert(ctx, G, nh, WD_F64, P.c, WD_F64, r));
+        rr = cc;
+        ww = -1.0;
+        if (P.bhat) {
+            WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.bhat, true));
+            ww = ctx->hres[0];
+        }
+    } else {
+        WD_TRY(true_residual(P, x, r, &rr, &ww));
+        info->operator_applies++;
+    }
     auto converged = [&]() { return P.bhat ? ww <= target_w : rr <= target_r; };
     wd_status status = WD_ENOCONV;
     if (converged()) status = WD_OK;
@@ -147,7 +157,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
         double rr_s = rr, maxrr = rr;
         while (info->iters < prm.maxiter) {
             // A p = M^dag (M p), and <p, A p> = ||M p||^2 summed by the kernel that writes M p
-            WD_TRY(op_M_norm(P.g, P.kappa, P.subset, pop, p, mp, 0));
+            WD_TRY(op_M_red(P.g, P.kappa, P.subset, pop, p, mp, RED_NORM, nullptr, 0));
             WD_TRY(op_M(P.g, P.kappa, P.subset, 1, pop, 1, mp, ap));
             WD_TRY(fetch_results(ctx, 1));
             info->operator_applies++;

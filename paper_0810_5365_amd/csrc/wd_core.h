@@ -61,7 +61,7 @@ inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (
 // Reliable-update threshold: delta < 0 selects the default for the sloppy precision.
 inline double default_delta(int prec)
 {
-    return prec == WD_F32 ? 1e-3 : (prec == WD_F16 ? 1e-2 : (prec == WD_BF16 ? 3e-2 : 0.1));
+    return prec == WD_F32 ? 1e-4 : (prec == WD_F16 ? 1e-2 : (prec == WD_BF16 ? 3e-2 : 0.1));
 }
 inline double resolve_delta(double delta, int prec) { return delta < 0.0 ? default_delta(prec) : delta; }
 inline size_t halves_of(int subset, int nrhs) { return (size_t)nrhs * (subset == WD_FULL ? 2 : 1); }
@@ -120,11 +120,16 @@ struct DslashCall {
 };
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
-wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp, double* nrm,
-                              int* nblocks);
-// The same launch with |out|^2 summed per workgroup into partials[0 .. *nblocks)
-// (the caller sizes partials for one sum per workgroup of 64 sites and rhs).
-wd_status launch_dslash_norm(wd_context ctx, const Geom& g, const DslashCall& c, double* partials, int* nblocks);
+// tuning-table key of a launch
+std::string dslash_key(const Geom& g, const DslashCall& c);
+// ---- dslash_red.hip: a fused-update launch (c.x set, no dagger, one rhs) that also sums a
+// reduction of its result per workgroup: RED_NORM |out|^2 (1 value); RED_XDOT <out, x> and
+// |out|^2, RED_YDOT <y, out> and |out|^2 (3 values; y a half field at c.prec).  Value v of
+// workgroup k lands in partials[v * nblocks + k]; the caller sizes partials for 3 values per
+// workgroup of 64 sites.
+enum { RED_NORM = 1, RED_XDOT = 2, RED_YDOT = 3 };
+wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, int red, const void* y,
+                            double* partials, int* nblocks);
 // ---- dslash_mrhs.hip: 16 rhs per wave with the colour multiply on the matrix cores ----
 bool mrhs_eligible(const DslashCall& c);
 wd_status launch_dslash_mrhs(wd_context ctx, const Geom& g, const DslashCall& c);
@@ -155,8 +160,11 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, con
 // r = b - y (all float64) and ||r||^2 -> dres[0]
 wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
-// dres[slot] (and hres) = the sum of partials[0 .. nblk), in a fixed order; not fetched
-wd_status reduce_partials(wd_context ctx, int nblk, int slot);
+// true when the float64 field (nhalves half fields) is all zeros (a norm sweep; false on error)
+bool is_zero_f64(wd_context ctx, const Geom& g, size_t nhalves, const void* x);
+// dres[slot + v] (and hres) = the sum of partials[v * nblk .. (v + 1) * nblk) for v < n, in a
+// fixed order; not fetched
+wd_status reduce_partials(wd_context ctx, int nblk, int n, int slot);
 // out = sum_{i < n} (cre[i] + i cim[i]) x[i], n <= 3, out may alias an input; with r0 non-null also
 // ||out||^2 and <r0, out> (dres/hres 0; 1, 2)
 wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nhalves, int prec, int n, const void* const* x,

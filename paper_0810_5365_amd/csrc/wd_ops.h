@@ -13,9 +13,12 @@ wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, cons
                     double a, double b);
 // M (FULL) or Mhat (EVEN / ODD), or their daggers
 wd_status op_M(wd_gauge g, double kappa, int subset, int dagger, int prec, int nrhs, const void* in, void* out);
-// out = M in (FULL) or Mhat in (EVEN / ODD), one rhs, with ||out||^2 summed in the last
-// launch into dres[slot] and hres[slot] (not fetched: synchronise before reading hres)
-wd_status op_M_norm(wd_gauge g, double kappa, int subset, int prec, const void* in, void* out, int slot);
+// out = Mhat in (EVEN / ODD) or M in (FULL, RED_NORM only), one rhs, with the reduction `red`
+// of the result (RED_NORM ||out||^2; RED_XDOT <out, in>, ||out||^2; RED_YDOT <y, out>,
+// ||out||^2) summed by the last launch into dres[slot ..] and hres[slot ..] (not fetched:
+// synchronise before reading hres)
+wd_status op_M_red(wd_gauge g, double kappa, int subset, int prec, const void* in, void* out, int red, const void* y,
+                   int slot);
 // M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD)
 wd_status op_MdagM(wd_gauge g, double kappa, int subset, int prec, int nrhs, const void* in, void* out);
 
