@@ -272,12 +272,25 @@ def _check_field(t, lat, subset, prec, nrhs):
         raise ValueError("field buffer holds %d bytes, needs %d" % (got, need))
 
 
+def _canon_reals(lat, subset, nrhs):
+    """float64 count of a canonical spinor field (nrhs x sites x 4 x 3 complex)."""
+    v = int(np.prod(list(lat.dims)))
+    return int(nrhs) * (v if int(subset) == FULL else v // 2) * 24
+
+
+def _check_canon(n, lat, subset, nrhs):
+    need = _canon_reals(lat, subset, nrhs)
+    if n != need:
+        raise ValueError("canonical field holds %d reals, the lattice, subset and nrhs need %d" % (n, need))
+
+
 def pack(ctx, lat, subset, prec, canon, nrhs=1):
     """canonical complex (numpy, host) or float64 (torch, device) -> new packed device field."""
     import torch
     if isinstance(canon, np.ndarray):
         canon = torch.from_numpy(np.ascontiguousarray(canon, dtype=np.complex128).view(np.float64)).to(
             "cuda:%d" % ctx.device)
+    _check_canon(canon.numel() * canon.element_size() // 8, lat, subset, nrhs)
     out = new_field(lat, subset, prec, nrhs, ctx.device)
     wd_spinor_pack(ctx.handle, ctypes.byref(lat), int(subset), int(prec), int(nrhs), ctypes.c_void_p(canon.data_ptr()),
                    ctypes.c_void_p(out.data_ptr()))
@@ -289,6 +302,7 @@ def unpack(ctx, lat, subset, prec, packed, shape, nrhs=1):
     import torch
     _check_field(packed, lat, subset, prec, nrhs)
     n = int(np.prod(shape)) * 2
+    _check_canon(n, lat, subset, nrhs)
     canon = torch.empty(n, dtype=torch.float64, device="cuda:%d" % ctx.device)
     wd_spinor_unpack(ctx.handle, ctypes.byref(lat), int(subset), int(prec), int(nrhs), ctypes.c_void_p(packed.data_ptr()),
                      ctypes.c_void_p(canon.data_ptr()))
@@ -304,6 +318,9 @@ def pack_features(ctx, lat, canon, channels, nsamples=1):
     """canonical complex (nsamples, C, T, Z, Y, X, 3) on the host -> packed float32 device features."""
     import torch
     c = torch.from_numpy(np.ascontiguousarray(canon, dtype=np.complex128).view(np.float64)).to("cuda:%d" % ctx.device)
+    if c.numel() != int(nsamples) * int(channels) * int(np.prod(list(lat.dims))) * 6:
+        raise ValueError("canonical features hold %d reals, need %d" % (
+            c.numel(), int(nsamples) * int(channels) * int(np.prod(list(lat.dims))) * 6))
     out = torch.empty(feature_bytes(lat, channels, nsamples) // 4, dtype=torch.float32, device="cuda:%d" % ctx.device)
     wd_feature_pack(ctx.handle, ctypes.byref(lat), int(channels), int(nsamples), c.data_ptr(), out.data_ptr())
     return out
@@ -312,6 +329,8 @@ def pack_features(ctx, lat, canon, channels, nsamples=1):
 def unpack_features(ctx, lat, packed, shape, channels, nsamples=1):
     import torch
     n = int(np.prod(shape)) * 2
+    if n != int(nsamples) * int(channels) * int(np.prod(list(lat.dims))) * 6:
+        raise ValueError("feature shape %s does not match %d samples of %d channels" % (shape, nsamples, channels))
     canon = torch.empty(n, dtype=torch.float64, device="cuda:%d" % ctx.device)
     wd_feature_unpack(ctx.handle, ctypes.byref(lat), int(channels), int(nsamples), packed.data_ptr(), canon.data_ptr())
     torch.cuda.current_stream(ctx.device).synchronize()
