@@ -69,8 +69,9 @@ def measured_traffic(dims):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(U, psi_e, dims):
-    """The FP64 oracle's Mhat^dagger Mhat on the same inputs (one application)."""
+def cpu_baseline(U, psi_e, dims, gpu_out=None):
+    """The FP64 oracle's Mhat^dagger Mhat on the same inputs (one application), and the
+    relative L2 distance of the benchmark step's FP32 output from it."""
     import oracle as orc
     Vh = psi_e.shape[0]
     orc.parity_sites(dims, 0)
@@ -78,7 +79,7 @@ def cpu_baseline(U, psi_e, dims):
     t0 = time.perf_counter()
     reps = 0
     while True:
-        orc.mhat_dag_mhat(U, psi_e, KAPPA, BC)
+        ref = orc.mhat_dag_mhat(U, psi_e, KAPPA, BC)
         reps += 1
         if time.perf_counter() - t0 > 10.0 or reps >= 3:
             break
@@ -87,7 +88,8 @@ def cpu_baseline(U, psi_e, dims):
     return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": orc.num_threads(), "kind": "oracle",
             "sample": "%d application(s) of the FP64 oracle's Mhat^dag Mhat on the full %dx%dx%dx%d lattice "
                       "(%d even sites), %.2f s each" % (reps, *dims, Vh, dt),
-            "one_core": cpu_one_core()}
+            "one_core": cpu_one_core(),
+            "step_rel_l2_vs_oracle": None if gpu_out is None else float(orc.rel_l2(gpu_out, ref))}
 
 
 _ONE_CORE = r"""
@@ -527,6 +529,8 @@ def main():
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     ms_per_step = ms / args.steps
+    # the step's output, for the comparison with the oracle (before anything else writes fout)
+    step_out = None if args.no_cpu else w.unpack(ctx, lat, w.EVEN, w.F32, fout, psi_e.shape)
 
     # the plain even-odd dslash D_eo alone (no fused update), same timing method
     fodd = w.new_field(lat, w.ODD, w.F32)
@@ -637,7 +641,7 @@ def main():
         rec["slab_32c8_of_32c64"] = slab_extras(w, ctx, stream, torch, ls, U)
     if not args.no_cpu:
         print("bench: timing the CPU oracle baseline", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(U, psi_e, dims)
+        rec["cpu_baseline"] = cpu_baseline(U, psi_e, dims, step_out)
         rec["cpu_baseline"]["host"] = platform.processor() or platform.machine()
     print(json.dumps(rec), flush=True)
     g.close()
