@@ -183,8 +183,8 @@ wd_status hop_half(wd_gauge g, int prec, int par, int dagger, int nrhs, const vo
                          half_call(g, links, prec, par, dagger, nrhs, in, in_stride, out, out_stride, x, x_stride, a, b));
 }
 
-wd_status op_M_red(wd_gauge g, double kappa, int subset, int prec, const void* in, void* out, int red, const void* y,
-                   int slot)
+wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out, int red,
+                   const void* y, int slot)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -192,27 +192,29 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int prec, const void* i
     const void* links = nullptr;
     WD_TRY(gauge_links(g, prec, &links));
     WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
-    if (subset == WD_FULL) {   // out_p = in_p - kappa D in_{1-p}, both parities, sums side by side
-        if (red != RED_NORM) {
-            set_error("fused reduction %d: only the norm is built for the full lattice", red);
+    if (subset == WD_FULL) {   // out_p = in_p - kappa D in_{1-p} for both parities, their sums side by side
+        if (red_values(red) != 1) {
+            set_error("fused reduction %d: not built for the full lattice", red);
             return WD_EUNSUPPORTED;
         }
-        int n0 = 0, n1 = 0;
-        WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, 0, 0, 1, (const char*)in + hb, 2 * hb, out, 2 * hb,
-                                                   in, 2 * hb, 1.0, -kappa), red, nullptr, ctx->partials, &n0));
-        WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, 1, 0, 1, in, 2 * hb, (char*)out + hb, 2 * hb,
-                                                   (const char*)in + hb, 2 * hb, 1.0, -kappa), red, nullptr,
-                                 ctx->partials + n0, &n1));
-        return reduce_partials(ctx, n0 + n1, 1, slot);
+        int n[2] = {0, 0};
+        for (int par = 0; par < 2; ++par) {
+            const char* yp = y ? (const char*)y + par * hb : nullptr;
+            WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, (const char*)in + (1 - par) * hb,
+                                                       2 * hb, (char*)out + par * hb, 2 * hb,
+                                                       (const char*)in + par * hb, 2 * hb, 1.0, -kappa),
+                                     red, yp, ctx->partials + n[0], &n[par]));
+        }
+        return reduce_partials(ctx, n[0] + n[1], 1, slot);
     }
     void* tmp = nullptr;
     WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
     const int par = subset == WD_EVEN ? 0 : 1;
     int n = 0;
-    WD_TRY(hop_half(g, prec, 1 - par, 0, 1, in, hb, tmp, hb, nullptr, 0, 0.0, 1.0));
-    WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, 0, 1, tmp, hb, out, hb, in, hb, 1.0, -kappa * kappa),
-                             red, y, ctx->partials, &n));
-    return reduce_partials(ctx, n, red == RED_NORM ? 1 : 3, slot);
+    WD_TRY(hop_half(g, prec, 1 - par, dagger, 1, in, hb, tmp, hb, nullptr, 0, 0.0, 1.0));
+    WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, tmp, hb, out, hb, in, hb, 1.0,
+                                               -kappa * kappa), red, y, ctx->partials, &n));
+    return reduce_partials(ctx, n, red_values(red), slot);
 }
 
 wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, const void* in, void* out, const void* x,

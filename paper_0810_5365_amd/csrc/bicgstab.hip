@@ -21,9 +21,8 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     const int ps = prm.sloppy;   // storage of the iteration's vectors; arithmetic in float32 (float64 for F64)
     const double delta = resolve_delta(prm.delta, ps);
     const size_t hs = half_bytes(G, ps), h64 = half_bytes(G, WD_F64);
-    void *r, *t64, *rs, *r0, *p, *v, *s, *t, *xs;
+    void *r, *rs, *r0, *p, *v, *s, *t, *xs;
     WD_TRY(ws_get(ctx, "bicg.r", h64, &r));
-    WD_TRY(ws_get(ctx, "bicg.t64", h64, &t64));
     WD_TRY(ws_get(ctx, "bicg.rs", hs, &rs));
     WD_TRY(ws_get(ctx, "bicg.r0", hs, &r0));
     WD_TRY(ws_get(ctx, "bicg.p", hs, &p));
@@ -33,8 +32,8 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     WD_TRY(ws_get(ctx, "bicg.xs", hs, &xs));
     const double target = prm.tol * prm.tol * bnorm2;
     auto true_res = [&](double* rr) -> wd_status {
-        WD_TRY(op_M(g, kappa, WD_EVEN, 0, WD_F64, 1, x, t64));
-        WD_TRY(blas_xmy_norm(ctx, G, 1, bhat, t64, r, true));
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x, r, RED_RESID, bhat, 0));   // r = bhat - Mhat x, ||r||^2
+        WD_TRY(fetch_results(ctx, 1));
         *rr = ctx->hres[0];
         info->operator_applies++;
         return WD_OK;
@@ -82,7 +81,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
             WD_TRY(blas_lincomb(ctx, G, 1, ps, 3, in, cr, ci, p, nullptr, false));
         }
         // v = Mhat p with <r0, v> summed by the launch that writes v
-        WD_TRY(op_M_red(g, kappa, WD_EVEN, ps, p, v, RED_YDOT, r0, 0));
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, ps, p, v, RED_YDOT, r0, 0));
         WD_TRY(fetch_results(ctx, 2));
         const cd r0v(ctx->hres[0], ctx->hres[1]);
         alpha = rho_new / r0v;
@@ -92,7 +91,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
             WD_TRY(blas_lincomb(ctx, G, 1, ps, 2, in, cr, ci, s, nullptr, false));
         }
         // t = Mhat s with <t, s> and ||t||^2 summed by the launch that writes t (s is its a x term)
-        WD_TRY(op_M_red(g, kappa, WD_EVEN, ps, s, t, RED_XDOT, nullptr, 0));
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, ps, s, t, RED_XDOT, nullptr, 0));
         WD_TRY(fetch_results(ctx, 3));
         info->operator_applies += 2;
         const cd ts(ctx->hres[0], ctx->hres[1]);
@@ -187,11 +186,10 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
         WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
     }
     WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
-    void *t, *r;
-    WD_TRY(ws_get(ctx, "wilson.t", 2 * hb, &t));
+    void* r;
     WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
-    WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
-    WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
+    WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
+    WD_TRY(fetch_results(ctx, 1));
     info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
     info->operator_applies++;
     info->status = s;

@@ -65,6 +65,8 @@ template <int P> __device__ __forceinline__ void quant_roundtrip(float* v)
 //   RED_NORM  |out|^2                        -> r[0]
 //   RED_XDOT  <out, x>, |out|^2              -> r[0] + i r[1], r[2]
 //   RED_YDOT  <y, out> (y = A.y), |out|^2    -> r[0] + i r[1], r[2]
+//   RED_RESID out = y - (a x + b D in), |out|^2 -> r[0]   (a residual, stored instead)
+//   RED_YDIFF |y - out|^2                    -> r[0]
 template <typename T>
 __device__ __forceinline__ void site_dot_norm(const T* a, const T* b, const T* o, double* r)
 {
@@ -222,21 +224,37 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= b;
     }
+    if constexpr (RED == 4) {   // the residual y - (a x + b D in) is what is stored
+        T yv[24];
+        SpinorIO<P>::load(A.y + rhs * A.out_stride, A.g.ps, cb, yv);
+#pragma unroll
+        for (int k = 0; k < 24; ++k) acc[k] = yv[k] - acc[k];
+    }
     SpinorIO<P>::store(A.out + rhs * A.out_stride, A.g.ps, cb, acc);
     if constexpr (RED > 0) {
         // the reduction sees the values a later load returns (16-bit: the codes times the scale)
         if constexpr (P == P_F16 || P == P_BF16) quant_roundtrip<P>(acc);
-        if constexpr (RED == 1) {
+        if constexpr (RED == 1 || RED == 4) {
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < 24; ++k) s += (double)acc[k] * (double)acc[k];
             red[0] = s;
         } else if constexpr (RED == 2) {
             site_dot_norm(acc, xv, acc, red);
-        } else {
+        } else if constexpr (RED == 3) {
             T yv[24];
             SpinorIO<P>::load(A.y + rhs * A.out_stride, A.g.ps, cb, yv);
             site_dot_norm(yv, acc, acc, red);
+        } else {
+            T yv[24];
+            SpinorIO<P>::load(A.y + rhs * A.out_stride, A.g.ps, cb, yv);
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < 24; ++k) {
+                const double d = (double)yv[k] - (double)acc[k];
+                s += d * d;
+            }
+            red[0] = s;
         }
     }
 }

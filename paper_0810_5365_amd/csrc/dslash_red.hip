@@ -8,10 +8,10 @@
 
 namespace wd {
 
-template <int P, int R, bool NT, bool PF, int RED>
+template <int P, int R, bool DAG, bool NT, bool PF, int RED>
 __global__ void __launch_bounds__(256) dslash_red_kernel(DslashArgs A)
 {
-    constexpr int NV = RED == RED_NORM ? 1 : 3;
+    constexpr int NV = red_values(RED);
     const uint32_t bid = A.remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
     const uint32_t i = bid * blockDim.x + threadIdx.x;
     double v[3] = {0.0, 0.0, 0.0};
@@ -19,9 +19,9 @@ __global__ void __launch_bounds__(256) dslash_red_kernel(DslashArgs A)
         if (A.zb > 0) {
             int c[4];
             const uint32_t cb = zblock_site(A, i, c);
-            dslash_site<P, R, false, true, NT, PF, RED>(A, cb, c, 0, v);
+            dslash_site<P, R, DAG, true, NT, PF, RED>(A, cb, c, 0, v);
         } else {
-            dslash_site<P, R, false, true, NT, PF, RED>(A, i, 0, v);
+            dslash_site<P, R, DAG, true, NT, PF, RED>(A, i, 0, v);
         }
     }
     __shared__ double lds[NV][4];
@@ -43,28 +43,46 @@ __global__ void __launch_bounds__(256) dslash_red_kernel(DslashArgs A)
     }
 }
 
-template <int P, int R>
-static wd_status launch_pr(wd_context ctx, const DslashArgs& A, const TuneParam& tp, int red, unsigned nblk)
+template <int P, int R, bool DAG, int RED>
+static wd_status launch_k(wd_context ctx, const DslashArgs& A, const TuneParam& tp, unsigned nblk)
 {
     const dim3 grid(nblk), block(tp.block);
-    const int sel = (tp.nt ? 1 : 0) | (tp.pf ? 2 : 0) | ((red - 1) << 2);
-    switch (sel) {
-#define WD_RK(K) case K: hipLaunchKernelGGL((dslash_red_kernel<P, R, (K & 1) != 0, (K & 2) != 0, (K >> 2) + 1>), \
-                                            grid, block, 0, ctx->stream, A); break;
-    WD_RK(0) WD_RK(1) WD_RK(2) WD_RK(3) WD_RK(4) WD_RK(5) WD_RK(6) WD_RK(7) WD_RK(8) WD_RK(9) WD_RK(10) WD_RK(11)
-#undef WD_RK
-    default: set_error("dslash: bad fused reduction %d", red); return WD_EINVAL;
+    switch ((tp.nt ? 1 : 0) | (tp.pf ? 2 : 0)) {
+    case 0: hipLaunchKernelGGL((dslash_red_kernel<P, R, DAG, false, false, RED>), grid, block, 0, ctx->stream, A); break;
+    case 1: hipLaunchKernelGGL((dslash_red_kernel<P, R, DAG, true, false, RED>), grid, block, 0, ctx->stream, A); break;
+    case 2: hipLaunchKernelGGL((dslash_red_kernel<P, R, DAG, false, true, RED>), grid, block, 0, ctx->stream, A); break;
+    default: hipLaunchKernelGGL((dslash_red_kernel<P, R, DAG, true, true, RED>), grid, block, 0, ctx->stream, A); break;
     }
     WD_LAUNCHED();
     return WD_OK;
 }
 
+// The solvers' inner products (RED_NORM, RED_XDOT, RED_YDOT) are built without the dagger for
+// every precision; the float64 residuals (RED_RESID, RED_YDIFF) with and without it, in F64.
+template <int P, int R>
+static wd_status launch_pr(wd_context ctx, const DslashArgs& A, const TuneParam& tp, int red, bool dag, unsigned nblk)
+{
+    if (red <= RED_YDOT) {
+        if (dag) return WD_EUNSUPPORTED;
+        switch (red) {
+        case RED_NORM: return launch_k<P, R, false, RED_NORM>(ctx, A, tp, nblk);
+        case RED_XDOT: return launch_k<P, R, false, RED_XDOT>(ctx, A, tp, nblk);
+        default: return launch_k<P, R, false, RED_YDOT>(ctx, A, tp, nblk);
+        }
+    }
+    if constexpr (P == P_F64) {
+        if (red == RED_RESID)
+            return dag ? launch_k<P, R, true, RED_RESID>(ctx, A, tp, nblk) : launch_k<P, R, false, RED_RESID>(ctx, A, tp, nblk);
+        return dag ? launch_k<P, R, true, RED_YDIFF>(ctx, A, tp, nblk) : launch_k<P, R, false, RED_YDIFF>(ctx, A, tp, nblk);
+    }
+    return WD_EUNSUPPORTED;
+}
+
 wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, int red, const void* y,
                             double* partials, int* nblocks)
 {
-    if (!c.x || c.dagger || c.nrhs != 1 || red < RED_NORM || red > RED_YDOT || (red == RED_YDOT && !y) || !partials ||
-        !nblocks) {
-        set_error("dslash: a fused reduction needs a x + b D in, no dagger, one rhs (and y for <y, out>)");
+    if (!c.x || c.nrhs != 1 || red < RED_NORM || red > RED_YDIFF || (red >= RED_YDOT && !y) || !partials || !nblocks) {
+        set_error("dslash: a fused reduction needs a x + b D in, one rhs (and y for RED_YDOT, RED_RESID, RED_YDIFF)");
         return WD_EINVAL;
     }
     // the launch shape tuned for the same launch without the reduction
@@ -73,21 +91,26 @@ wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, 
     DslashArgs A;
     WD_TRY(dslash_setup(g, c, tp, &A));
     const unsigned nblk = (unsigned)((g.Vh + tp.block - 1) / tp.block);
-    if ((size_t)nblk * (red == RED_NORM ? 1 : 3) > ctx->npartials) {
+    if ((size_t)nblk * red_values(red) > ctx->npartials) {
         set_error("dslash: %u workgroup sums do not fit the %zu reduction slots", nblk, ctx->npartials);
         return WD_EINVAL;
     }
     A.red = partials;
     A.y = (const char*)y;
     *nblocks = (int)nblk;
-    const bool r12 = c.recon == 12;
+    const bool r12 = c.recon == 12, dag = c.dagger != 0;
+    wd_status st = WD_EINVAL;
     switch (c.prec) {
-    case WD_F64: return r12 ? launch_pr<P_F64, 12>(ctx, A, tp, red, nblk) : launch_pr<P_F64, 18>(ctx, A, tp, red, nblk);
-    case WD_F32: return r12 ? launch_pr<P_F32, 12>(ctx, A, tp, red, nblk) : launch_pr<P_F32, 18>(ctx, A, tp, red, nblk);
-    case WD_F16: return r12 ? launch_pr<P_F16, 12>(ctx, A, tp, red, nblk) : launch_pr<P_F16, 18>(ctx, A, tp, red, nblk);
-    case WD_BF16: return r12 ? launch_pr<P_BF16, 12>(ctx, A, tp, red, nblk) : launch_pr<P_BF16, 18>(ctx, A, tp, red, nblk);
+    case WD_F64: st = r12 ? launch_pr<P_F64, 12>(ctx, A, tp, red, dag, nblk) : launch_pr<P_F64, 18>(ctx, A, tp, red, dag, nblk); break;
+    case WD_F32: st = r12 ? launch_pr<P_F32, 12>(ctx, A, tp, red, dag, nblk) : launch_pr<P_F32, 18>(ctx, A, tp, red, dag, nblk); break;
+    case WD_F16: st = r12 ? launch_pr<P_F16, 12>(ctx, A, tp, red, dag, nblk) : launch_pr<P_F16, 18>(ctx, A, tp, red, dag, nblk); break;
+    case WD_BF16: st = r12 ? launch_pr<P_BF16, 12>(ctx, A, tp, red, dag, nblk) : launch_pr<P_BF16, 18>(ctx, A, tp, red, dag, nblk); break;
     default: set_error("dslash: bad precision %d", c.prec); return WD_EINVAL;
     }
+    if (st == WD_EUNSUPPORTED)
+        set_error("dslash: fused reduction %d is built for %s only", red,
+                  red <= RED_YDOT ? "the launch without the dagger" : "float64");
+    return st;
 }
 
 } // namespace wd

@@ -68,7 +68,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     const size_t nh = 1;   // Krylov vectors: EVEN half fields
     const size_t v32 = half_bytes(G, WD_F32);
     const size_t h64 = half_bytes(G, WD_F64);
-    void *V, *Z, *wv, *e, *e64, *rhat, *r, *t, *fa = nullptr, *fb = nullptr;
+    void *V, *Z, *wv, *e, *e64, *rhat, *r, *fa = nullptr, *fb = nullptr;
     WD_TRY(ws_get(ctx, "fgmres.V", v32 * (m + 1), &V));
     WD_TRY(ws_get(ctx, "fgmres.Z", v32 * m, &Z));
     WD_TRY(ws_get(ctx, "fgmres.w", v32, &wv));
@@ -76,7 +76,6 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     WD_TRY(ws_get(ctx, "fgmres.e64", h64, &e64));
     WD_TRY(ws_get(ctx, "fgmres.rhat", h64, &rhat));
     WD_TRY(ws_get(ctx, "fgmres.r", 2 * h64, &r));
-    WD_TRY(ws_get(ctx, "fgmres.t", 2 * h64, &t));
     if (net) {
         int cmax = 0;
         for (int c : net->widths) cmax = c > cmax ? c : cmax;
@@ -112,16 +111,16 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     // so the float64 refinement only needs the Schur residual (two hops per cycle).
     WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, (long long)h64, bhat, (long long)h64, b_e, (long long)h64, 1.0, kappa));
     auto schur_res = [&](double* rr) -> wd_status {
-        WD_TRY(op_M(g, kappa, WD_EVEN, 0, WD_F64, 1, x_e, t));
-        WD_TRY(blas_xmy_norm(ctx, G, 1, bhat, t, rhat, true));
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x_e, rhat, RED_RESID, bhat, 0));   // rhat = bhat - Mhat x_e
+        WD_TRY(fetch_results(ctx, 1));
         *rr = ctx->hres[0];
         info->operator_applies++;
         return WD_OK;
     };
     auto finish_x = [&](double* rr) -> wd_status {   // x_o, then the full residual in float64
         WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, (long long)h64, x_o, (long long)h64, b_o, (long long)h64, 1.0, kappa));
-        WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
-        WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
+        WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
+        WD_TRY(fetch_results(ctx, 1));
         *rr = ctx->hres[0];
         info->operator_applies++;
         return WD_OK;

@@ -79,20 +79,16 @@ static wd_status true_residual(const CGProblem& P, const void* x, void* r, doubl
     const Geom& G = P.g->geom;
     const size_t nh = halves_of(P.subset, 1);
     const size_t bytes = half_bytes(G, WD_F64) * nh;
-    void *t1, *t2;
+    void* t1;
     WD_TRY(ws_get(ctx, "cg.t1", bytes, &t1));
-    WD_TRY(ws_get(ctx, "cg.t2", bytes, &t2));
-    if (P.bhat) {
-        WD_TRY(op_M(P.g, P.kappa, P.subset, 0, WD_F64, 1, x, t1));
-        WD_TRY(blas_xmy_norm(ctx, G, nh, P.bhat, t1, t2, true));
-        *ww = ctx->hres[0];
-        WD_TRY(op_M(P.g, P.kappa, P.subset, 1, WD_F64, 1, t1, t2));
-    } else {
-        WD_TRY(op_MdagM(P.g, P.kappa, P.subset, WD_F64, 1, x, t2));
-        *ww = -1.0;
-    }
-    WD_TRY(blas_xmy_norm(ctx, G, nh, P.c, t2, r, true));
+    // t1 = M x (with ||bhat - t1||^2 when tracked), then r = c - M^dag t1 with ||r||^2, each
+    // difference and norm taken by the launch that produces the operator's result
+    if (P.bhat) WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, WD_F64, x, t1, RED_YDIFF, P.bhat, 1));
+    else WD_TRY(op_M(P.g, P.kappa, P.subset, 0, WD_F64, 1, x, t1));
+    WD_TRY(op_M_red(P.g, P.kappa, P.subset, 1, WD_F64, t1, r, RED_RESID, P.c, 0));
+    WD_TRY(fetch_results(ctx, 2));
     *rr = ctx->hres[0];
+    *ww = P.bhat ? ctx->hres[1] : -1.0;
     return WD_OK;
 }
 
@@ -157,7 +153,7 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
         double rr_s = rr, maxrr = rr;
         while (info->iters < prm.maxiter) {
             // A p = M^dag (M p), and <p, A p> = ||M p||^2 summed by the kernel that writes M p
-            WD_TRY(op_M_red(P.g, P.kappa, P.subset, pop, p, mp, RED_NORM, nullptr, 0));
+            WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, pop, p, mp, RED_NORM, nullptr, 0));
             WD_TRY(op_M(P.g, P.kappa, P.subset, 1, pop, 1, mp, ap));
             WD_TRY(fetch_results(ctx, 1));
             info->operator_applies++;
@@ -298,11 +294,10 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     if (s != WD_OK && s != WD_ENOCONV) return s;
     // x_o = b_o + kappa D_oe x_e ; then the full-system residual in float64
     WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
-    void *t, *r;
-    WD_TRY(ws_get(ctx, "wilson.t", 2 * hb, &t));
+    void* r;
     WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
-    WD_TRY(op_M(g, kappa, WD_FULL, 0, WD_F64, 1, x, t));
-    WD_TRY(blas_xmy_norm(ctx, G, 2, b, t, r, true));
+    WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
+    WD_TRY(fetch_results(ctx, 1));
     info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
     info->operator_applies++;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

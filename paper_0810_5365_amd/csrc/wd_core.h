@@ -122,12 +122,15 @@ wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c);
 wd_status launch_dslash_tuned(wd_context ctx, const Geom& g, const DslashCall& c, const TuneParam& tp);
 // tuning-table key of a launch
 std::string dslash_key(const Geom& g, const DslashCall& c);
-// ---- dslash_red.hip: a fused-update launch (c.x set, no dagger, one rhs) that also sums a
-// reduction of its result per workgroup: RED_NORM |out|^2 (1 value); RED_XDOT <out, x> and
-// |out|^2, RED_YDOT <y, out> and |out|^2 (3 values; y a half field at c.prec).  Value v of
-// workgroup k lands in partials[v * nblocks + k]; the caller sizes partials for 3 values per
-// workgroup of 64 sites.
-enum { RED_NORM = 1, RED_XDOT = 2, RED_YDOT = 3 };
+// ---- dslash_red.hip: a fused-update launch (c.x set, one rhs) that also sums a reduction of
+// its result per workgroup: RED_NORM |out|^2 (1 value); RED_XDOT <out, x> and |out|^2,
+// RED_YDOT <y, out> and |out|^2 (3 values; y a half field at c.prec); these without the
+// dagger.  In float64, with or without the dagger: RED_RESID stores out = y - (a x + b D in)
+// and sums |out|^2; RED_YDIFF sums |y - out|^2 (1 value each).  Value v of workgroup k lands
+// in partials[v * nblocks + k]; the caller sizes partials for 3 values per workgroup of 64
+// sites.
+enum { RED_NORM = 1, RED_XDOT = 2, RED_YDOT = 3, RED_RESID = 4, RED_YDIFF = 5 };
+constexpr int red_values(int red) { return red == RED_XDOT || red == RED_YDOT ? 3 : 1; }
 wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, int red, const void* y,
                             double* partials, int* nblocks);
 // ---- dslash_mrhs.hip: 16 rhs per wave with the colour multiply on the matrix cores ----

@@ -13,12 +13,13 @@ wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, cons
                     double a, double b);
 // M (FULL) or Mhat (EVEN / ODD), or their daggers
 wd_status op_M(wd_gauge g, double kappa, int subset, int dagger, int prec, int nrhs, const void* in, void* out);
-// out = Mhat in (EVEN / ODD) or M in (FULL, RED_NORM only), one rhs, with the reduction `red`
-// of the result (RED_NORM ||out||^2; RED_XDOT <out, in>, ||out||^2; RED_YDOT <y, out>,
-// ||out||^2) summed by the last launch into dres[slot ..] and hres[slot ..] (not fetched:
-// synchronise before reading hres)
-wd_status op_M_red(wd_gauge g, double kappa, int subset, int prec, const void* in, void* out, int red, const void* y,
-                   int slot);
+// out = Mhat in (EVEN / ODD) or M in (FULL), or their daggers, one rhs, with the reduction
+// `red` of the result summed by the last launch(es) into dres[slot ..] and hres[slot ..] (not
+// fetched: synchronise before reading hres): RED_NORM ||out||^2; RED_XDOT <out, in>,
+// ||out||^2 and RED_YDOT <y, out>, ||out||^2 (EVEN / ODD, no dagger); RED_RESID out = y - M in
+// with ||out||^2, RED_YDIFF ||y - M in||^2 (F64).  y has the subset of out.
+wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out, int red,
+                   const void* y, int slot);
 // M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD)
 wd_status op_MdagM(wd_gauge g, double kappa, int subset, int prec, int nrhs, const void* in, void* out);
 
