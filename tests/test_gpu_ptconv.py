@@ -194,3 +194,37 @@ def test_forward_matrix_core_path(env, cin, cout, monkeypatch):
         err = orc.rel_l2(got[s], orc.ptconv_forward(U, phi[s], Wref.astype(np.complex128), BC))
         assert err < 1e-2, err
         assert err > 1e-6          # it did run in bf16
+
+
+@pytest.mark.parametrize("cin,cout", [(4, 8), (8, 4)])
+def test_matrix_core_wave_orders_agree(cin, cout, monkeypatch):
+    """The matrix-core layer in the natural and the z-blocked wave order (depths 2 and 4 on a
+    16 x 8 x 8 x 8 lattice, where X Y / 2 = 64) gives bit-identical outputs, and matches the
+    oracle to the bf16 bound."""
+    import torch
+    from paper_0810_5365_amd import wdirac as w
+    monkeypatch.setenv("WD_PTCONV_MFMA", "1")
+    dims = (16, 8, 8, 8)
+    X, Y, Z, T = dims
+    ctx = w.Context(0)
+    U = ls.gauge_field(dims, 0.7, 5003)
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(U)
+    lat = w.lattice(dims, BC)
+    phi = ls.gaussian_complex((1, cin, T, Z, Y, X, 3), 107)
+    W = ls.gaussian_complex((9, cout, cin), 109)
+    Wq = as_torch_weights(W).to(torch.bfloat16).contiguous()
+    fin = w.pack_features(ctx, lat, phi, cin, 1)
+    outs = []
+    for zb in ("0", "2", "4"):
+        monkeypatch.setenv("WD_PTCONV_ZB", zb)
+        out = w.pack_features(ctx, lat, np.zeros((1, cout, T, Z, Y, X, 3), complex), cout, 1)
+        w.wd_ptconv_forward(g.handle, cin, cout, w.BF16, 1, Wq.data_ptr(), fin.data_ptr(), out.data_ptr())
+        torch.cuda.synchronize()
+        outs.append(out.clone())
+    assert torch.equal(outs[0], outs[1]) and torch.equal(outs[0], outs[2])
+    Wref = orc.round16(W.real.astype(np.float32), "bf16") + 1j * orc.round16(W.imag.astype(np.float32), "bf16")
+    got = w.unpack_features(ctx, lat, outs[2], (1, cout, T, Z, Y, X, 3), cout, 1)
+    assert orc.rel_l2(got[0], orc.ptconv_forward(U, phi[0], Wref.astype(np.complex128), BC)) < 1e-2
+    g.close()
+    ctx.close()
