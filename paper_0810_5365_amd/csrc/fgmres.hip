@@ -45,19 +45,25 @@ static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, v
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
-    WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true, true));
-    // WD_PTCONV_PARITY_SKIP=0 computes every path and site (same result, for checking)
+    // WD_PTCONV_PARITY_SKIP=0 computes every path and site through the feature tensors (same
+    // result, for checking)
     const char* env = getenv("WD_PTCONV_PARITY_SKIP");
     const bool skip = !(env && atoi(env) == 0);
+    const int L = net.nlayers;
+    // the first and last layers read and write the spinor half fields themselves when they can
+    const bool sin = skip && ptconv_spin_io(net.wprec, net.widths[0], net.widths[1]);
+    const bool sout = skip && ptconv_spin_io(net.wprec, net.widths[L - 1], net.widths[L]);
+    if (!sin) WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true, true));
     void* cur = fa;
     void* nxt = fb;
-    for (int l = 0; l < net.nlayers; ++l) {
+    for (int l = 0; l < L; ++l) {
         // the input's odd sites are zero, and only the even output sites are used
         WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1,
-                          skip && l == 0 ? 1 : -1, skip && l == net.nlayers - 1));
+                          skip && l == 0 ? 1 : -1, skip && l == L - 1, sin && l == 0 ? v : nullptr,
+                          sout && l == L - 1 ? z : nullptr));
         std::swap(cur, nxt);
     }
-    return launch_spinor_features(ctx, G, 1, z, cur, false, true);
+    return sout ? WD_OK : launch_spinor_features(ctx, G, 1, z, cur, false, true);
 }
 
 static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& prm, int m, const Net* net, const void* b,

@@ -44,7 +44,20 @@ struct PTArgs {
     // close in time; needs X Y / 2 a multiple of 64 and zb dividing Z.
     int zb = 0;
     FastDiv dplane, dzb, dt;
+    // Matrix-core path, 4 spin channels: spin_in reads the input's even sites straight from an
+    // EVEN float32 spinor half field (its odd sites are zero: zero_par = 1), spin_out writes the
+    // even output sites into one (even_out), in place of the feature tensors.
+    const char* spin_in = nullptr;
+    char* spin_out = nullptr;
 };
+
+// float2 index of (channel = spin b, colour k) of site cb in a float32 spinor half field:
+// real (3 b + k) 2 of 24 sits in float4 plane (3 b + k) / 2, half (3 b + k) % 2.
+__device__ __forceinline__ size_t spin_f2(int b, int k, int ps, uint32_t cb)
+{
+    const int r = 3 * b + k;
+    return ((size_t)(r >> 1) * ps + cb) * 2 + (r & 1);
+}
 
 // First checkerboard site of the 64 consecutive sites i0 .. i0 + 63 of the z-blocked order
 // i = r + (X/2) Y (zi + zb (t + T b)), z = b zb + zi (r < X Y / 2, a multiple of 64).
@@ -408,7 +421,7 @@ template <int R, int CIN> struct MfRaw {
     float2 v[CIN][3];            // neighbour features, channel b, colour k
 };
 
-template <int PATH, int R, int CIN>
+template <int PATH, int R, int CIN, bool SIN>
 __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
                                         MfRaw<R, CIN>& x)
 {
@@ -427,6 +440,14 @@ __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int p
         if constexpr (R == 18) x.l18 = ((const float2*)(grp - (FWD ? cb : nb) + (size_t)4 * A.g.ps))[FWD ? cb : nb];
         src = nb;
         spar = 1 - par;
+    }
+    if constexpr (SIN) {   // only even sources are ever loaded (the odd ones are skipped as zero)
+        const float2* sp = (const float2*)A.spin_in;
+#pragma unroll
+        for (int b = 0; b < CIN; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x.v[b][k] = sp[spin_f2(b, k, A.g.ps, src)];
+        return;
     }
     // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
     const float2* site = in + (size_t)spar * 3 * Vh + src;
@@ -488,17 +509,18 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
 }
 
 // paths P..LAST, each one's loads issued before the previous one's arithmetic
-template <int P, int LAST, int R, int CIN>
+template <int P, int LAST, int R, int CIN, bool SIN>
 __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
                                         int lane, uint16_t* B, const bf16x4* Af, f32x4* acc, MfRaw<R, CIN>& cur,
                                         MfRaw<R, CIN>& nxt)
 {
-    if constexpr (P < LAST) mf_load<P + 1, R, CIN>(A, in, par, cb, c, nxt);
+    if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN>(A, in, par, cb, c, nxt);
     mf_compute<P, R, CIN>(A, c, lane, B, cur, Af[P], acc);
-    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
+    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
 }
 
-template <int R, int CIN, int COUT>
+// SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out)
+template <int R, int CIN, int COUT, bool SIN, bool SOUT>
 __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
@@ -553,22 +575,28 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
     MfRaw<R, CIN> ra, rb;
     if (skip_hops) {
-        mf_load<0, R, CIN>(A, in, par, cb, c, ra);
+        mf_load<0, R, CIN, SIN>(A, in, par, cb, c, ra);
         mf_compute<0, R, CIN>(A, c, lane, B, ra, Af[0], acc);
     } else if (skip_stay) {
-        mf_load<1, R, CIN>(A, in, par, cb, c, ra);
-        mf_pipe<1, 8, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<1, R, CIN, SIN>(A, in, par, cb, c, ra);
+        mf_pipe<1, 8, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     } else {
-        mf_load<0, R, CIN>(A, in, par, cb, c, ra);
-        mf_pipe<0, 8, R, CIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<0, R, CIN, SIN>(A, in, par, cb, c, ra);
+        mf_pipe<0, 8, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     }
     const int g = lane >> 4;
+    float2* so = (float2*)A.spin_out;
 #pragma unroll
     for (int t = 0; t < 12; ++t) {
         const int n = t * 16 + (lane & 15);
         const int k = n >> 6;
         const uint32_t scb = cb0 + (n & 63);
         if (scb >= Vh) continue;
+        if constexpr (SOUT) {   // even outputs straight into the spinor half field
+            if (2 * g < COUT) so[spin_f2(2 * g, k, A.g.ps, scb)] = make_float2(acc[t][0], acc[t][1]);
+            if (2 * g + 1 < COUT) so[spin_f2(2 * g + 1, k, A.g.ps, scb)] = make_float2(acc[t][2], acc[t][3]);
+            continue;
+        }
         if (2 * g < COUT) out[fidx(2 * g, par, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
         if (2 * g + 1 < COUT) out[fidx(2 * g + 1, par, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
     }
@@ -579,10 +607,21 @@ static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int 
 {
     const int waves = (A.out_sites > A.g.Vh ? 2 : 1) * ((A.g.Vh + 63) / 64);
     dim3 grid((waves + 3) / 4, nsamples), block(256);
-    if (cin == 4 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8>), grid, block, 0, ctx->stream, A);
-    else if (cin == 8 && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8>), grid, block, 0, ctx->stream, A);
-    else if (cin == 8 && cout == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4>), grid, block, 0, ctx->stream, A);
-    else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4>), grid, block, 0, ctx->stream, A);
+    const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
+    if (cin == 4 && cout == 8) {
+        if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, false, false>), grid, block, 0, ctx->stream, A);
+    } else if (cin == 8 && cout == 8) {
+        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false>), grid, block, 0, ctx->stream, A);
+    } else if (cin == 8 && cout == 4) {
+        if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, false>), grid, block, 0, ctx->stream, A);
+    } else {
+        if (si && so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, true>), grid, block, 0, ctx->stream, A);
+        else if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, false>), grid, block, 0, ctx->stream, A);
+        else if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, true>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, false>), grid, block, 0, ctx->stream, A);
+    }
     WD_LAUNCHED();
     return WD_OK;
 }
@@ -605,6 +644,8 @@ static bool use_mfma(int wprec, int cin, int cout)
     return !(e && atoi(e) == 0);
 }
 
+bool ptconv_spin_io(int wprec, int cin, int cout) { return use_mfma(wprec, cin, cout); }
+
 // ---- launchers ---------------------------------------------------------------------------
 template <int R, int WP>
 static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples)
@@ -621,8 +662,14 @@ static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples
 }
 
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
-                            int nsamples, int zero_par, bool even_out)
+                            int nsamples, int zero_par, bool even_out, const void* spin_in, void* spin_out)
 {
+    if ((spin_in || spin_out) && !(ptconv_spin_io(wprec, cin, cout) && nsamples == 1 &&
+                                   (!spin_in || (cin == 4 && zero_par == 1)) && (!spin_out || (cout == 4 && even_out)))) {
+        set_error("ptconv: spinor input/output needs the matrix-core path, 4 spin channels, one sample, "
+                  "a zero odd input half and even outputs only");
+        return WD_EINVAL;
+    }
     const void* links;
     WD_TRY(gauge_links(g, WD_F32, &links));
     PTArgs A;
@@ -636,6 +683,8 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
     A.out_sample = (long long)cout * 6 * g->geom.Vh;
     A.zero_par = zero_par;
     A.out_sites = even_out ? g->geom.Vh : 2 * g->geom.Vh;
+    A.spin_in = (const char*)spin_in;
+    A.spin_out = (char*)spin_out;
     {
         const Geom& G = g->geom;
         const int zb = ptconv_zblock(G);
