@@ -369,72 +369,6 @@ wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nh, int pacc, const vo
     return WD_OK;
 }
 
-// r = b - y, ||r||^2 (float64 fields)
-__global__ void __launch_bounds__(RED_BLOCK) xmy_norm_kernel(SiteRange B, SiteRange Y, SiteRange R, long long nsites,
-                                                             double* partials)
-{
-    double acc[1] = {0.0};
-    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
-        const long long h = k / B.Vh;
-        const uint32_t cb = (uint32_t)(k - h * B.Vh);
-        double b[24], y[24];
-        SpinorIO<P_F64>::load(B.half(h), B.ps, cb, b);
-        SpinorIO<P_F64>::load(Y.half(h), B.ps, cb, y);
-#pragma unroll
-        for (int i = 0; i < 24; ++i) {
-            b[i] -= y[i];
-            acc[0] += b[i] * b[i];
-        }
-        SpinorIO<P_F64>::store((char*)R.half(h), B.ps, cb, b);
-    }
-    block_reduce<1>(acc, partials);
-}
-
-wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nh, const void* b, const void* y, void* r, bool fetch)
-{
-    const long long n = (long long)nh * g.Vh;
-    const int nblk = red_blocks(n);
-    WD_TRY(ensure_reduction(ctx, (size_t)nblk));
-    const size_t hb = half_bytes(g, WD_F64);
-    SiteRange B{(const char*)b, g.Vh, g.ps, hb}, Y{(const char*)y, g.Vh, g.ps, hb}, R{(const char*)r, g.Vh, g.ps, hb};
-    hipLaunchKernelGGL(xmy_norm_kernel, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, Y, R, n, ctx->partials);
-    WD_LAUNCHED();
-    return finish(ctx, nblk, 1, fetch);
-}
-
-// ---- y = a x + b y with complex a, b --------------------------------------------------------
-template <int P>
-__global__ void cxpby_kernel(SiteRange X, SiteRange Y, long long n, double ar, double ai, double br, double bi)
-{
-    WD_SITE_LOOP(n, X.Vh)
-    using T = typename RealOf<P>::T;
-    T x[24], y[24];
-    SpinorIO<P>::load(X.half(h), X.ps, cb, x);
-    SpinorIO<P>::load(Y.half(h), Y.ps, cb, y);
-    const T a0 = (T)ar, a1 = (T)ai, b0 = (T)br, b1 = (T)bi;
-#pragma unroll
-    for (int q = 0; q < 12; ++q) {
-        const T xr = x[2 * q], xi = x[2 * q + 1], yr = y[2 * q], yi = y[2 * q + 1];
-        y[2 * q] = a0 * xr - a1 * xi + b0 * yr - b1 * yi;
-        y[2 * q + 1] = a0 * xi + a1 * xr + b0 * yi + b1 * yr;
-    }
-    SpinorIO<P>::store((char*)Y.half(h), Y.ps, cb, y);
-}
-
-wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nh, int prec, double ar, double ai, const void* x, double br,
-                     double bi, void* y)
-{
-    const long long n = (long long)nh * g.Vh;
-    SiteRange X{(const char*)x, g.Vh, g.ps, half_bytes(g, prec)}, Y{(const char*)y, g.Vh, g.ps, half_bytes(g, prec)};
-    switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(cxpby_kernel<P_F64>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
-    case WD_F32: hipLaunchKernelGGL(cxpby_kernel<P_F32>, site_grid(n), dim3(256), 0, ctx->stream, X, Y, n, ar, ai, br, bi); break;
-    default: set_error("cxpby: precision %d not supported (F32, F64 only)", prec); return WD_EUNSUPPORTED;
-    }
-    WD_LAUNCHED();
-    return WD_OK;
-}
-
 // ---- fused linear combinations (BiCGstab) ------------------------------------------------
 // out = sum_{i < n} c_i X_i (complex c_i, n <= 3; out may be one of the X_i).  RED adds the
 // reductions ||out||^2 and <R0, out> (values 0, 1, 2 = ||out||^2, Re, Im), so one sweep both
@@ -518,45 +452,6 @@ wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nh, int prec, int n
     WD_LAUNCHED();
     if (r0) return finish(ctx, nblk, 3, fetch);
     return WD_OK;
-}
-
-// <a, b> (values 0, 1) and ||a||^2 (value 2) in one sweep
-template <int P>
-__global__ void __launch_bounds__(RED_BLOCK) dot_norm_kernel(SiteRange A, SiteRange B, long long nsites, double* partials)
-{
-    double acc[3] = {0.0, 0.0, 0.0};
-    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
-        const long long h = k / A.Vh;
-        const uint32_t cb = (uint32_t)(k - h * A.Vh);
-        typename RealOf<P>::T a[24], b[24];
-        SpinorIO<P>::load(A.half(h), A.ps, cb, a);
-        SpinorIO<P>::load(B.half(h), A.ps, cb, b);
-#pragma unroll
-        for (int i = 0; i < 12; ++i) {
-            const double ar = a[2 * i], ai = a[2 * i + 1], br = b[2 * i], bi = b[2 * i + 1];
-            acc[0] += ar * br + ai * bi;
-            acc[1] += ar * bi - ai * br;
-            acc[2] += ar * ar + ai * ai;
-        }
-    }
-    block_reduce<3>(acc, partials);
-}
-
-wd_status blas_dot_norm(wd_context ctx, const Geom& g, size_t nh, int prec, const void* a, const void* b, bool fetch)
-{
-    const long long n = (long long)nh * g.Vh;
-    const int nblk = red_blocks(n);
-    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 3));
-    SiteRange A{(const char*)a, g.Vh, g.ps, half_bytes(g, prec)}, B{(const char*)b, g.Vh, g.ps, half_bytes(g, prec)};
-    switch (prec) {
-    case WD_F64: hipLaunchKernelGGL(dot_norm_kernel<P_F64>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
-    case WD_F32: hipLaunchKernelGGL(dot_norm_kernel<P_F32>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
-    case WD_F16: hipLaunchKernelGGL(dot_norm_kernel<P_F16>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
-    case WD_BF16: hipLaunchKernelGGL(dot_norm_kernel<P_BF16>, dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, A, B, n, ctx->partials); break;
-    default: set_error("dot_norm: bad precision %d", prec); return WD_EINVAL;
-    }
-    WD_LAUNCHED();
-    return finish(ctx, nblk, 3, fetch);
 }
 
 // ---- block Gram-Schmidt helpers (flexible GMRES) ---------------------------------------

@@ -149,9 +149,6 @@ wd_status launch_convert(wd_context ctx, const Geom& g, size_t nhalves, int sp, 
 wd_status blas_dot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, const void* b, bool fetch);
 wd_status blas_norm2(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, bool fetch);
 wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, double ar, double ai, const void* x, void* y);
-// y = a x + b y, complex a = (ar, ai), b = (br, bi); F32 and F64
-wd_status blas_cxpby(wd_context ctx, const Geom& g, size_t nhalves, int prec, double ar, double ai, const void* x, double br,
-                     double bi, void* y);
 wd_status blas_zero(wd_context ctx, const Geom& g, size_t nhalves, int prec, void* x);
 // y = a*x + b*y with real a, b (y, x may differ in precision: x at px, y at py)
 wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nhalves, int px, const void* x, double a, int py, void* y, double b);
@@ -160,8 +157,6 @@ wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nhalves, int pacc, vo
                      const void* ap, double alpha, bool fetch);
 // CG step: p = r + beta p (r at pacc, p at pop)
 wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, const void* r, int pop, void* p, double beta);
-// r = b - y (all float64) and ||r||^2 -> dres[0]
-wd_status blas_xmy_norm(wd_context ctx, const Geom& g, size_t nhalves, const void* b, const void* y, void* r, bool fetch);
 wd_status fetch_results(wd_context ctx, int n);
 // true when the float64 field (nhalves half fields) is all zeros (a norm sweep; false on error)
 bool is_zero_f64(wd_context ctx, const Geom& g, size_t nhalves, const void* x);
@@ -172,8 +167,6 @@ wd_status reduce_partials(wd_context ctx, int nblk, int n, int slot);
 // ||out||^2 and <r0, out> (dres/hres 0; 1, 2)
 wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nhalves, int prec, int n, const void* const* x,
                        const double* cre, const double* cim, void* out, const void* r0, bool fetch);
-// <a, b> (dres/hres 0, 1) and ||a||^2 (2) in one sweep
-wd_status blas_dot_norm(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* a, const void* b, bool fetch);
 // h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[slot + 2i],
 // dres[slot + 2i + 1] (and hres); with_norm adds ||w||^2 in dres[slot + 2k]
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
