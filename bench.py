@@ -626,6 +626,10 @@ def main():
         "copy_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "tuned_launch": tuned,
+        # the paper's own figures (Section 1 and Section 7), on other hardware: context only
+        "context_paper_gflops": {"wilson_dslash_tesla_c870": 68, "wilson_dslash_gtx_280": 92,
+                                 "eo_operator_tesla_c870": ">60", "eo_operator_gtx_280": "~90",
+                                 "cg_tesla_c870": ">50", "cg_gtx_280": ">80", "sse_cpu_xeon": "<5"},
     }
     if not args.no_extras:
         print("bench: multi-rhs and ragged-batch measurements", file=sys.stderr, flush=True)
