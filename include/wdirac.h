@@ -359,6 +359,15 @@ int wd_tune_get(wd_context ctx, const char* key, int* out6);
  * 12-real links, a multiple of 16 rhs); returns 1, or 0 if the key is absent. */
 int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n);
 
+/* ---- environment overrides (measurement and testing; results do not change) ----
+ * WD_DSLASH_BLOCK, _REMAP, _NT, _PF, _RHS_INNER, _ZB  launch shape of an untuned dslash
+ * WD_DSLASH_MFMA = 0 / 1   16-bit multi-rhs dslash off / on the matrix cores, tuned or not
+ * WD_BATCH_PF = 1          software-pipelined directions in the persistent batch kernel
+ * WD_PTCONV_MFMA = 0       PT-conv channel mixing on the vector units even with bf16 weights
+ * WD_PTCONV_ZB = depth     z-block depth of the matrix-core PT-conv wave order (0: natural)
+ * WD_PTCONV_PARITY_SKIP = 0  the network inside FGMRES computes every path and site and
+ *                          goes through the feature tensors (the same result, for checking) */
+
 #ifdef __cplusplus
 }
 #endif
