@@ -11,7 +11,7 @@ Prints one JSON line with the throughput, the roofline of the dslash kernel
 events on the stream the kernels run on) and the FP64 CPU oracle timed on
 the host on the same operator.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--shape-sweep-only]
 """
 import argparse
 import json
@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-rhs and ragged-batch measurements")
     ap.add_argument("--no-sweep", action="store_true", help="skip the L^3 x 2L volume sweep")
+    ap.add_argument("--shape-sweep-only", action="store_true",
+                    help="only the EO dslash over lattices one extent short of 32^3 x 64 (for counter runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning table: loaded if it exists (no tuning), else tuned and written there")
     return ap.parse_args()
@@ -157,37 +159,45 @@ def timed_repeats(fn, stream, torch, n=100, repeats=5, warmup=10):
     return float(np.median(us)), float(min(us))
 
 
-def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20):
-    """FP32 12-real EO dslash on L^3 x 2L lattices: warm (5 x 100 back-to-back launches,
-    median and minimum) and, where the compulsory working set fits the 256 MB
-    last-level cache, single launches timed alone, warm and cold (after 1 GiB of
-    other traffic).  The links
-    are the sub-box of the 32^3 x 64 field: i.i.d. per link, so each is a field of
-    the same distribution."""
+# lattices one extent short of 32^3 x 64 (and 28^4 x 2): the rate against the extents
+SHAPE_SWEEP = ((24, 32, 32, 64), (28, 32, 32, 64), (30, 32, 32, 64), (32, 24, 32, 64), (32, 28, 32, 64),
+               (32, 32, 28, 64), (32, 32, 32, 56), (28, 28, 28, 56), (32, 32, 32, 64))
+
+
+def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20, shapes=None):
+    """FP32 12-real EO dslash on L^3 x 2L lattices (or the given X x Y x Z x T shapes):
+    warm (5 x 100 back-to-back launches, median and minimum) and, where the compulsory
+    working set fits the 256 MB last-level cache, single launches timed alone, warm and
+    cold (after 1 GiB of other traffic).  The links are the sub-box of the 32^3 x 64
+    field: i.i.d. per link, so each is a field of the same distribution."""
     import numpy as np
     scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
     scrub2 = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     rows = []
-    for L in sizes:
-        dims = (L, L, L, 2 * L)
-        Vh = L ** 3 * L
-        if 2 * L > U.shape[1] or L > U.shape[4]:
+    for dims in (shapes if shapes is not None else [(L, L, L, 2 * L) for L in sizes]):
+        X, Y, Z, T = dims
+        Vh = X * Y * Z * T // 2
+        if T > U.shape[1] or Z > U.shape[2] or Y > U.shape[3] or X > U.shape[4]:
             continue
         g = w.Gauge(ctx, dims, BC, w.RECON_12)
-        g.upload(np.ascontiguousarray(U[:, :2 * L, :L, :L, :L]))
+        g.upload(np.ascontiguousarray(U[:, :T, :Z, :Y, :X]))
         g.prepare(w.F32)
         lat = w.lattice(dims, BC)
-        fin = w.pack(ctx, lat, w.ODD, w.F32, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, L), ls.STREAM_SPINOR))
+        fin = w.pack(ctx, lat, w.ODD, w.F32, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, X), ls.STREAM_SPINOR))
         fout = w.new_field(lat, w.EVEN, w.F32)
-        w.wd_autotune_dslash(g.handle, w.F32, 1, None)
+        if shapes is None or w.tune_get(ctx, w.dslash_key(dims, w.F32, 12, 1, 0, 0)) is None:
+            w.wd_autotune_dslash(g.handle, w.F32, 1, None)   # (a loaded tuning table is kept)
         run = lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fin.data_ptr(), fout.data_ptr())
         med, mn = timed_repeats(run, stream, torch)
         ws = Vh * BYTES_DSLASH
-        row = {"L": L, "lattice": "%dx%dx%dx%d" % dims, "even_sites": Vh, "working_set_mb": round(ws / 1e6, 1),
+        row = {"lattice": "%dx%dx%dx%d" % dims, "even_sites": Vh, "working_set_mb": round(ws / 1e6, 1),
                "warm_us_median": round(med, 3), "warm_us_min": round(mn, 3),
                "warm_gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1),
-               "warm_frac_hbm": round(ws / med / 1e3 / HBM_PEAK_GBS, 4)}
+               "warm_frac_hbm": round(ws / med / 1e3 / HBM_PEAK_GBS, 4),
+               "tuned": w.tune_get(ctx, w.dslash_key(dims, w.F32, 12, 1, 0, 0))}
+        if shapes is None:
+            row["L"] = X
         if ws < mall_bytes:
             # one launch at a time between events: first with the data left in the caches by
             # the previous launch, then after evicting it (a 1 GiB write, then a 1 GiB read so
@@ -214,7 +224,7 @@ def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32)
         del fin, fout
         g.close()
     del scrub, scrub2
-    return {"kernel": "dslash_kernel<F32, r12>, autotuned per size", "bytes_per_site": BYTES_DSLASH, "rows": rows}
+    return {"kernel": "dslash_kernel<F32, r12>, autotuned per lattice", "bytes_per_site": BYTES_DSLASH, "rows": rows}
 
 
 def slab_extras(w, ctx, stream, torch, ls, U, nslab=8, link_gbs=153.0):
@@ -494,6 +504,18 @@ def main():
     print("bench: generating %s links and source" % (dims,), file=sys.stderr, flush=True)
     U = ls.gauge_field(dims, EPS, ls.link_seed(2))
     psi_e = ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2), ls.STREAM_SPINOR)
+    if args.shape_sweep_only:
+        # with --tune-cache: the launch shapes of an earlier run are loaded (so that a counter run
+        # under a profiler times the same configurations), else tuned and saved there
+        have = bool(args.tune_cache) and os.path.exists(args.tune_cache)
+        if have:
+            w.wd_tune_load(ctx.handle, args.tune_cache.encode())
+        sweep = volume_sweep(w, ctx, stream, torch, ls, U, shapes=SHAPE_SWEEP)
+        if args.tune_cache and not have:
+            w.wd_tune_save(ctx.handle, args.tune_cache.encode())
+        print(json.dumps({"shape_sweep": sweep}), flush=True)
+        ctx.close()
+        return
     g = w.Gauge(ctx, dims, BC, w.RECON_12)
     g.upload(U)
     g.prepare(w.F32)
@@ -641,6 +663,8 @@ def main():
     if not args.no_extras and not args.no_sweep and dims == DIMS:
         print("bench: volume sweep L^3 x 2L", file=sys.stderr, flush=True)
         rec["volume_sweep"] = volume_sweep(w, ctx, stream, torch, ls, U)
+        print("bench: lattices one extent short of 32^3 x 64", file=sys.stderr, flush=True)
+        rec["shape_sweep"] = volume_sweep(w, ctx, stream, torch, ls, U, shapes=SHAPE_SWEEP)
         print("bench: one t-slab of eight with half-spinor faces", file=sys.stderr, flush=True)
         rec["slab_32c8_of_32c64"] = slab_extras(w, ctx, stream, torch, ls, U)
     if not args.no_cpu:
