@@ -420,6 +420,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         d["restart"], d["delta"] = 16, 1e-4
         out[name] = d
     g.close()
+    out["network_apply_even"] = network_apply_times(w, ctx, net, dims, reps=20)
     return out
 
 
@@ -451,6 +452,34 @@ def network_layer_times(w, ctx, net, dims, reps=100):
             "unique_bytes_per_site": {k: (int(k.split("->")[0]) + int(k.split("->")[1])) * 24 + 4 * 48 for k in res}}
 
 
+def network_apply_times(w, ctx, net, dims, reps=100):
+    """The preconditioner as the learned solve applies it (the even sites of N (v_e, 0)), with
+    the hidden features in bf16 (the default) and in float32: microseconds per application."""
+    import ctypes
+    import os
+    import torch
+    import lattice_synth as ls
+    f = __import__("paper_0810_5365_amd.learn", fromlist=["Field"]).Field(ctx, dims, 0.7, 6001)
+    stream = torch.cuda.current_stream(0)
+    lat = w.lattice(dims, BC)
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    fin = w.pack(ctx, lat, w.EVEN, w.F32, ls.gaussian_complex((Vh, 4, 3), 17, ls.STREAM_SPINOR))
+    fout = w.new_field(lat, w.EVEN, w.F32)
+    ws = net.storage()
+    widths = (ctypes.c_int * len(net.widths))(*net.widths)
+    ptrs = (ctypes.c_void_p * len(ws))(*[t.data_ptr() for t in ws])
+    run = lambda: w.wd_ptnet_apply_even(f.g.handle, len(ws), widths, ptrs, net.wprec, fin.data_ptr(), fout.data_ptr())
+    res = {}
+    for mode, env in (("bf16_hidden", None), ("f32_hidden", "1")):
+        if env:
+            os.environ["WD_PTNET_F32_FEATURES"] = env
+        med, mn = timed_repeats(run, stream, torch, n=reps)
+        os.environ.pop("WD_PTNET_F32_FEATURES", None)
+        res[mode] = {"us_median": round(med, 2), "us_min": round(mn, 2)}
+    f.close()
+    return {"lattice": list(dims), "widths": list(net.widths), **res}
+
+
 def learned_extras(w, ctx):
     """Time to an FP64-verified 1e-10 Wilson-system residual on 16^3 x 32 (eps 0.7, kappa 0.1248),
     four gauge fields unseen in training: plain FP32 CG (with FP64 reliable updates), flexible
@@ -480,6 +509,7 @@ def learned_extras(w, ctx):
                             "wall_ms": round(1e3 * float(np.mean([r[k]["wall_s"] for r in rows])), 3)}
     out["learned_speedup_vs_plain_cg"] = round(out["mean_plain_cg_f32"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
     out["network_layers"] = network_layer_times(w, ctx, net, dims)
+    out["network_apply_even"] = network_apply_times(w, ctx, net, dims)
     out["learned_speedup_vs_fgmres_no_net"] = round(out["mean_fgmres_no_net"]["wall_ms"] / out["mean_fgmres_learned"]["wall_ms"], 3)
     return out
 

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 2
+#define WD_ABI_VERSION 3
 
 typedef enum {
     WD_OK = 0,
@@ -334,6 +334,20 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
 wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
                           const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
                           wd_solver_info* info);
+/* The preconditioner of wd_fgmres_solve on its own: out = [N (in, 0)]_e, the even
+ * sites of the network applied to the EVEN float32 spinor half field `in` extended
+ * by zero odd sites (channel = spin, as in wd_spinor_to_features).  nlayers >= 1,
+ * widths and weights as for wd_fgmres_solve.  With BF16 weights the layers mix
+ * channels on the matrix cores (transported inputs rounded to bf16, float32
+ * accumulation); a 4 -> 8 -> ... -> 8 -> 4 network then also stores its hidden
+ * features as bf16 pairs, so each layer moves half the feature bytes.  in, out:
+ * distinct device pointers to EVEN F32 half fields (wd_spinor_bytes(lat, WD_EVEN,
+ * WD_F32, 1) bytes); the hidden features live in the context's workspace.
+ * Asynchronous on the context's stream.  WD_EINVAL: a null pointer, in == out, a
+ * network not mapping 4 to 4 channels, a bad weight precision; WD_EUNSUPPORTED: a
+ * width outside {1, 2, 3, 4, 8}. */
+wd_status wd_ptnet_apply_even(wd_gauge g, int nlayers, const int* widths, const void* const* weights, wd_prec wprec,
+                              const void* in, void* out);
 
 /* ---- launch-shape tuning --------------------------------------------------- */
 /* Time every launch shape of the dslash kernels used with gauge g at precision
@@ -359,14 +373,17 @@ int wd_tune_get(wd_context ctx, const char* key, int* out6);
  * 12-real links, a multiple of 16 rhs); returns 1, or 0 if the key is absent. */
 int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n);
 
-/* ---- environment overrides (measurement and testing; results do not change) ----
+/* ---- environment overrides (measurement and testing; results do not change, except as noted) ----
  * WD_DSLASH_BLOCK, _REMAP, _NT, _PF, _RHS_INNER, _ZB  launch shape of an untuned dslash
  * WD_DSLASH_MFMA = 0 / 1   16-bit multi-rhs dslash off / on the matrix cores, tuned or not
  * WD_BATCH_PF = 1          software-pipelined directions in the persistent batch kernel
  * WD_PTCONV_MFMA = 0       PT-conv channel mixing on the vector units even with bf16 weights
  * WD_PTCONV_ZB = depth     z-block depth of the matrix-core PT-conv wave order (0: natural)
  * WD_PTCONV_PARITY_SKIP = 0  the network inside FGMRES computes every path and site and
- *                          goes through the feature tensors (the same result, for checking) */
+ *                          goes through float32 feature tensors (for checking: the result of
+ *                          WD_PTNET_F32_FEATURES = 1)
+ * WD_PTNET_F32_FEATURES = 1  the network inside FGMRES keeps float32 hidden features where it
+ *                          would keep bf16 ones (changes the result within the bf16 rounding) */
 
 #ifdef __cplusplus
 }

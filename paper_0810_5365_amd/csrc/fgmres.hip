@@ -53,6 +53,12 @@ static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, v
     // the first and last layers read and write the spinor half fields themselves when they can
     const bool sin = skip && ptconv_spin_io(net.wprec, net.widths[0], net.widths[1]);
     const bool sout = skip && ptconv_spin_io(net.wprec, net.widths[L - 1], net.widths[L]);
+    // a 4 -> 8 -> ... -> 8 -> 4 network on the matrix cores keeps its hidden features in bf16
+    // (the layers round their transported inputs to bf16 for the matrix cores anyway); the
+    // feature tensors are the layers' only traffic besides the links
+    bool hf = sin && sout && L >= 2;
+    for (int l = 1; l < L; ++l) hf = hf && net.widths[l] == 8;
+    if (const char* e = getenv("WD_PTNET_F32_FEATURES")) hf = hf && atoi(e) == 0;
     if (!sin) WD_TRY(launch_spinor_features(ctx, G, 1, (void*)v, fa, true, true));
     void* cur = fa;
     void* nxt = fb;
@@ -60,7 +66,7 @@ static wd_status apply_net(wd_gauge g, const Net& net, const void* v, void* z, v
         // the input's odd sites are zero, and only the even output sites are used
         WD_TRY(ptconv_fwd(g, net.widths[l], net.widths[l + 1], net.wprec, net.W[l], cur, nxt, 1,
                           skip && l == 0 ? 1 : -1, skip && l == L - 1, sin && l == 0 ? v : nullptr,
-                          sout && l == L - 1 ? z : nullptr));
+                          sout && l == L - 1 ? z : nullptr, hf));
         std::swap(cur, nxt);
     }
     return sout ? WD_OK : launch_spinor_features(ctx, G, 1, z, cur, false, true);
@@ -264,11 +270,59 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     return rr <= tol2 ? WD_OK : WD_ENOCONV;
 }
 
+// the network arguments of the C entry points, checked
+static wd_status make_net(const char* who, int nlayers, const int* widths, const void* const* weights, int wprec,
+                          Net* net)
+{
+    if (widths[0] != 4 || widths[nlayers] != 4) {
+        set_error("%s: the network must map 4 channels (spin) to 4 channels", who);
+        return WD_EINVAL;
+    }
+    if (wprec != WD_F32 && wprec != WD_F16 && wprec != WD_BF16) {
+        set_error("%s: weight precision %d not in {F32, F16, BF16}", who, wprec);
+        return WD_EINVAL;
+    }
+    net->nlayers = nlayers;
+    net->widths.assign(widths, widths + nlayers + 1);
+    net->W.assign(weights, weights + nlayers);
+    net->wprec = wprec;
+    for (int l = 0; l < nlayers; ++l) {
+        const int c = widths[l + 1];
+        if (!(c == 1 || c == 2 || c == 3 || c == 4 || c == 8) || !weights[l]) {
+            set_error("%s: layer %d: width %d unsupported or weights NULL", who, l, c);
+            return WD_EUNSUPPORTED;
+        }
+    }
+    return WD_OK;
+}
+
 } // namespace wd
 
 using namespace wd;
 
 extern "C" {
+
+wd_status wd_ptnet_apply_even(wd_gauge g, int nlayers, const int* widths, const void* const* weights, wd_prec wprec,
+                              const void* in, void* out)
+{
+    if (!g || nlayers < 1 || !widths || !weights || !in || !out || in == out) {
+        set_error("wd_ptnet_apply_even: bad argument");
+        return WD_EINVAL;
+    }
+    if (!g->uploaded) {
+        set_error("gauge field has not been uploaded");
+        return WD_EINVAL;
+    }
+    Net net;
+    WD_TRY(make_net("wd_ptnet_apply_even", nlayers, widths, weights, wprec, &net));
+    int cmax = 0;
+    for (int c : net.widths) cmax = c > cmax ? c : cmax;
+    const size_t fbytes = (size_t)cmax * 6 * g->geom.Vh * 2 * sizeof(float);
+    void *fa, *fb;
+    WD_TRY(ws_get(g->ctx, "fgmres.fa", fbytes, &fa));
+    WD_TRY(ws_get(g->ctx, "fgmres.fb", fbytes, &fb));
+    return apply_net(g, net, in, out, fa, fb);
+}
 
 wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
                           const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
@@ -288,23 +342,7 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
         return WD_EINVAL;
     }
     Net net;
-    if (nlayers > 0) {
-        if (widths[0] != 4 || widths[nlayers] != 4) {
-            set_error("wd_fgmres_solve: the network must map 4 channels (spin) to 4 channels");
-            return WD_EINVAL;
-        }
-        net.nlayers = nlayers;
-        net.widths.assign(widths, widths + nlayers + 1);
-        net.W.assign(weights, weights + nlayers);
-        net.wprec = wprec;
-        for (int l = 0; l < nlayers; ++l) {
-            const int c = widths[l + 1];
-            if (!(c == 1 || c == 2 || c == 3 || c == 4 || c == 8) || !weights[l]) {
-                set_error("wd_fgmres_solve: layer %d: width %d unsupported or weights NULL", l, c);
-                return WD_EUNSUPPORTED;
-            }
-        }
-    }
+    if (nlayers > 0) WD_TRY(make_net("wd_fgmres_solve", nlayers, widths, weights, wprec, &net));
     WD_HIP(hipStreamSynchronize(g->ctx->stream));
     const auto t0 = std::chrono::steady_clock::now();
     bool fallback = false;

@@ -421,7 +421,15 @@ template <int R, int CIN> struct MfRaw {
     float2 v[CIN][3];            // neighbour features, channel b, colour k
 };
 
-template <int PATH, int R, int CIN, bool SIN>
+// bf16 feature pair (re in the low half, as cvt_bf16x2 packs it) -> float2
+__device__ __forceinline__ float2 bf16x2_to_f2(uint32_t h)
+{
+    return make_float2(__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u));
+}
+
+// HF: the feature tensors (input and output, where not a spinor) hold bf16 pairs, one
+// uint32 per complex at the float2 layout's index
+template <int PATH, int R, int CIN, bool SIN, bool HF>
 __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
                                         MfRaw<R, CIN>& x)
 {
@@ -447,6 +455,14 @@ __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int p
         for (int b = 0; b < CIN; ++b)
 #pragma unroll
             for (int k = 0; k < 3; ++k) x.v[b][k] = sp[spin_f2(b, k, A.g.ps, src)];
+        return;
+    }
+    if constexpr (HF) {
+        const uint32_t* hs = (const uint32_t*)in + (size_t)spar * 3 * Vh + src;
+#pragma unroll
+        for (int b = 0; b < CIN; ++b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) x.v[b][k] = bf16x2_to_f2(hs[(size_t)(b * 6 + k) * Vh]);
         return;
     }
     // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
@@ -509,18 +525,19 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
 }
 
 // paths P..LAST, each one's loads issued before the previous one's arithmetic
-template <int P, int LAST, int R, int CIN, bool SIN>
+template <int P, int LAST, int R, int CIN, bool SIN, bool HF>
 __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
                                         int lane, uint16_t* B, const bf16x4* Af, f32x4* acc, MfRaw<R, CIN>& cur,
                                         MfRaw<R, CIN>& nxt)
 {
-    if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN>(A, in, par, cb, c, nxt);
+    if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN, HF>(A, in, par, cb, c, nxt);
     mf_compute<P, R, CIN>(A, c, lane, B, cur, Af[P], acc);
-    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
+    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
 }
 
-// SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out)
-template <int R, int CIN, int COUT, bool SIN, bool SOUT>
+// SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out);
+// HF: the feature tensors hold bf16 pairs (one sample)
+template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF>
 __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
@@ -575,14 +592,14 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
     MfRaw<R, CIN> ra, rb;
     if (skip_hops) {
-        mf_load<0, R, CIN, SIN>(A, in, par, cb, c, ra);
+        mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
         mf_compute<0, R, CIN>(A, c, lane, B, ra, Af[0], acc);
     } else if (skip_stay) {
-        mf_load<1, R, CIN, SIN>(A, in, par, cb, c, ra);
-        mf_pipe<1, 8, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<1, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
+        mf_pipe<1, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     } else {
-        mf_load<0, R, CIN, SIN>(A, in, par, cb, c, ra);
-        mf_pipe<0, 8, R, CIN, SIN>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
+        mf_pipe<0, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     }
     const int g = lane >> 4;
     float2* so = (float2*)A.spin_out;
@@ -597,30 +614,40 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
             if (2 * g + 1 < COUT) so[spin_f2(2 * g + 1, k, A.g.ps, scb)] = make_float2(acc[t][2], acc[t][3]);
             continue;
         }
+        if constexpr (HF) {
+            uint32_t* ho = (uint32_t*)out;
+            if (2 * g < COUT) ho[fidx(2 * g, par, k, Vh, scb)] = cvt_bf16x2(acc[t][0], acc[t][1]);
+            if (2 * g + 1 < COUT) ho[fidx(2 * g + 1, par, k, Vh, scb)] = cvt_bf16x2(acc[t][2], acc[t][3]);
+            continue;
+        }
         if (2 * g < COUT) out[fidx(2 * g, par, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
         if (2 * g + 1 < COUT) out[fidx(2 * g + 1, par, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
     }
 }
 
 template <int R>
-static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples)
+static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples, bool hf)
 {
     const int waves = (A.out_sites > A.g.Vh ? 2 : 1) * ((A.g.Vh + 63) / 64);
     dim3 grid((waves + 3) / 4, nsamples), block(256);
     const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
-    if (cin == 4 && cout == 8) {
-        if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, false, false>), grid, block, 0, ctx->stream, A);
+    if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
+        if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, true>), grid, block, 0, ctx->stream, A);
+        else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, true>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true>), grid, block, 0, ctx->stream, A);
+    } else if (cin == 4 && cout == 8) {
+        if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, false, false, false>), grid, block, 0, ctx->stream, A);
     } else if (cin == 8 && cout == 8) {
-        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false>), grid, block, 0, ctx->stream, A);
+        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, false>), grid, block, 0, ctx->stream, A);
     } else if (cin == 8 && cout == 4) {
-        if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, false>), grid, block, 0, ctx->stream, A);
+        if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, false, false>), grid, block, 0, ctx->stream, A);
     } else {
-        if (si && so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, true>), grid, block, 0, ctx->stream, A);
-        else if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, false>), grid, block, 0, ctx->stream, A);
-        else if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, true>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, false>), grid, block, 0, ctx->stream, A);
+        if (si && so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, true, false>), grid, block, 0, ctx->stream, A);
+        else if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, false, false>), grid, block, 0, ctx->stream, A);
+        else if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, true, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, false, false>), grid, block, 0, ctx->stream, A);
     }
     WD_LAUNCHED();
     return WD_OK;
@@ -662,8 +689,16 @@ static wd_status fwd_r_w(wd_context ctx, const PTArgs& A, int cout, int nsamples
 }
 
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out,
-                            int nsamples, int zero_par, bool even_out, const void* spin_in, void* spin_out)
+                            int nsamples, int zero_par, bool even_out, const void* spin_in, void* spin_out,
+                            bool half_feat)
 {
+    if (half_feat && !(ptconv_spin_io(wprec, cin, cout) && nsamples == 1 &&
+                       ((cin == 4 && cout == 8 && spin_in && !spin_out) || (cin == 8 && cout == 8 && !spin_in && !spin_out) ||
+                        (cin == 8 && cout == 4 && !spin_in && spin_out)))) {
+        set_error("ptconv: bf16 hidden features are built for the matrix-core layers of a 4 -> 8 -> ... -> 8 -> 4 "
+                  "network (spinor in first, spinor out last), one sample");
+        return WD_EINVAL;
+    }
     if ((spin_in || spin_out) && !(ptconv_spin_io(wprec, cin, cout) && nsamples == 1 &&
                                    (!spin_in || (cin == 4 && zero_par == 1)) && (!spin_out || (cout == 4 && even_out)))) {
         set_error("ptconv: spinor input/output needs the matrix-core path, 4 spin channels, one sample, "
@@ -696,7 +731,8 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
         }
     }
     const bool r12 = g->recon == 12;
-    if (use_mfma(wprec, cin, cout)) return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples) : mfma_r<18>(g->ctx, A, cin, cout, nsamples);
+    if (use_mfma(wprec, cin, cout))
+        return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples, half_feat) : mfma_r<18>(g->ctx, A, cin, cout, nsamples, half_feat);
     switch (wprec) {
     case WD_F32: return r12 ? fwd_r_w<12, P_F32>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F32>(g->ctx, A, cout, nsamples);
     case WD_F16: return r12 ? fwd_r_w<12, P_F16>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F16>(g->ctx, A, cout, nsamples);

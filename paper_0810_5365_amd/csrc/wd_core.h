@@ -189,9 +189,12 @@ wd_status blas_maxpy_dev(wd_context ctx, const Geom& g, size_t nhalves, int prec
 // that read only them); even_out: only the even output sites are needed.
 // spin_in / spin_out (matrix-core path, 4 spin channels, one sample): the input's even sites
 // come from an EVEN float32 spinor half field (zero_par = 1), the even outputs go into one
-// (even_out); ptconv_spin_io tells whether a layer shape can do that.
+// (even_out); ptconv_spin_io tells whether a layer shape can do that.  half_feat (matrix-core
+// path, one sample, the layers of a 4 -> 8 -> ... -> 8 -> 4 network with spinor input first and
+// spinor output last): the feature tensors in between hold bf16 pairs instead of float2.
 wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, const void* in, void* out, int nsamples,
-                     int zero_par = -1, bool even_out = false, const void* spin_in = nullptr, void* spin_out = nullptr);
+                     int zero_par = -1, bool even_out = false, const void* spin_in = nullptr, void* spin_out = nullptr,
+                     bool half_feat = false);
 bool ptconv_spin_io(int wprec, int cin, int cout);
 // FULL float32 spinor <-> 4-channel features; even_only: the spinor is one EVEN half
 // field (odd sites are zero on the way in and dropped on the way out).

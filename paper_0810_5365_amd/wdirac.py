@@ -101,6 +101,7 @@ _PROTOS = {
     "wd_device_copy": ("status", [_V, _V, _V, _S]),
     "wd_bicgstab_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
     "wd_fgmres_solve": ("status", [_V, _D, _P(WdSolverParams), _I, _I, _P(_I), _P(_V), _I, _V, _V, _P(WdSolverInfo)]),
+    "wd_ptnet_apply_even": ("status", [_V, _I, _P(_I), _P(_V), _I, _V, _V]),
     "wd_autotune_dslash": ("status", [_V, _I, _I, ctypes.c_char_p]),
     "wd_tune_save": ("status", [_V, ctypes.c_char_p]),
     "wd_tune_load": ("status", [_V, ctypes.c_char_p]),
@@ -112,7 +113,7 @@ _PROTOS = {
 }
 
 _lib = None
-ABI_VERSION = 2   # the structures above match include/wdirac.h at this version
+ABI_VERSION = 3   # the structures above match include/wdirac.h at this version
 
 
 def _raw():
