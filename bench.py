@@ -470,11 +470,12 @@ def network_apply_times(w, ctx, net, dims, reps=100):
     ptrs = (ctypes.c_void_p * len(ws))(*[t.data_ptr() for t in ws])
     run = lambda: w.wd_ptnet_apply_even(f.g.handle, len(ws), widths, ptrs, net.wprec, fin.data_ptr(), fout.data_ptr())
     res = {}
-    for mode, env in (("bf16_hidden", None), ("f32_hidden", "1")):
-        if env:
-            os.environ["WD_PTNET_F32_FEATURES"] = env
+    for mode, env in (("bf16_hidden", {}), ("bf16_hidden_last_layer_unsplit", {"WD_PTCONV_SPLIT": "0"}),
+                      ("f32_hidden", {"WD_PTNET_F32_FEATURES": "1"})):
+        os.environ.update(env)
         med, mn = timed_repeats(run, stream, torch, n=reps)
-        os.environ.pop("WD_PTNET_F32_FEATURES", None)
+        for k in env:
+            os.environ.pop(k, None)
         res[mode] = {"us_median": round(med, 2), "us_min": round(mn, 2)}
     f.close()
     return {"lattice": list(dims), "widths": list(net.widths), **res}

@@ -383,7 +383,10 @@ int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n);
  *                          goes through float32 feature tensors (for checking: the result of
  *                          WD_PTNET_F32_FEATURES = 1)
  * WD_PTNET_F32_FEATURES = 1  the network inside FGMRES keeps float32 hidden features where it
- *                          would keep bf16 ones (changes the result within the bf16 rounding) */
+ *                          would keep bf16 ones (changes the result within the bf16 rounding)
+ * WD_PTCONV_SPLIT = 0 / 1  the network's last layer (bf16 hidden features) splits each site
+ *                          group's paths over two waves never / always (default: on lattices of
+ *                          at most 2048 groups of 64 even sites; float32 summation order changes) */
 
 #ifdef __cplusplus
 }

@@ -536,22 +536,29 @@ __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int p
 }
 
 // SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out);
-// HF: the feature tensors hold bf16 pairs (one sample)
-template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF>
+// HF: the feature tensors hold bf16 pairs (one sample).
+// SPLIT (even outputs only, no zero parity): two waves share each 64-site group, the first
+// taking the stay path and the forward hops, the second the backward hops; the second's
+// accumulators are added to the first's through LDS.  With few sites (one wave per SIMD
+// otherwise) this halves each wave's chain of dependent path loads.
+template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF, bool SPLIT>
 __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
+    __shared__ f32x4 red[SPLIT ? 2 : 1][SPLIT ? 12 * 64 : 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     uint16_t* B = lds[wave];
     const uint32_t Vh = (uint32_t)A.g.Vh;
     // Every wave covers 64 consecutive checkerboard sites of one parity.  With both
     // parities computed, consecutive waves alternate parity over the same cb range, and
     // blocks run in XCD-contiguous order: the even and odd sites of one region (which read
-    // each other's features and share their links) fill the same L2.
+    // each other's features and share their links) fill the same L2.  Under SPLIT the two
+    // waves of a pair (0 and 1, 2 and 3 of a workgroup) cover one group.
     const bool both = A.out_sites > (int)Vh;
     const uint32_t gw = xcd_remap(blockIdx.x, gridDim.x) * 4 + wave;
-    const int par = both ? (int)(gw & 1) : 0;
-    const uint32_t i0 = (both ? gw >> 1 : gw) * 64;
+    const uint32_t gs = SPLIT ? gw >> 1 : gw;
+    const int par = both ? (int)(gs & 1) : 0;
+    const uint32_t i0 = (both ? gs >> 1 : gs) * 64;
     const uint32_t cb0 = A.zb > 0 ? zb_first(A, i0) : i0;
     // lanes past the end stage site 0 (in bounds); their columns are never stored
     const uint32_t cb = cb0 + lane < Vh ? cb0 + lane : 0;
@@ -591,7 +598,22 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     const bool skip_stay = A.zero_par >= 0 && par == A.zero_par;
     const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
     MfRaw<R, CIN> ra, rb;
-    if (skip_hops) {
+    if constexpr (SPLIT) {
+        f32x4* rs = red[wave >> 1];
+        if ((wave & 1) == 0) {
+            mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
+            mf_pipe<0, 4, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        } else {
+            mf_load<5, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
+            mf_pipe<5, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+#pragma unroll
+            for (int t = 0; t < 12; ++t) rs[t * 64 + lane] = acc[t];
+        }
+        __syncthreads();
+        if (wave & 1) return;
+#pragma unroll
+        for (int t = 0; t < 12; ++t) acc[t] += rs[t * 64 + lane];
+    } else if (skip_hops) {
         mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
         mf_compute<0, R, CIN>(A, c, lane, B, ra, Af[0], acc);
     } else if (skip_stay) {
@@ -608,7 +630,7 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
         const int n = t * 16 + (lane & 15);
         const int k = n >> 6;
         const uint32_t scb = cb0 + (n & 63);
-        if (scb >= Vh) continue;
+        if (scb >= Vh || i0 >= Vh) continue;   // (a wave past the last group stores nothing)
         if constexpr (SOUT) {   // even outputs straight into the spinor half field
             if (2 * g < COUT) so[spin_f2(2 * g, k, A.g.ps, scb)] = make_float2(acc[t][0], acc[t][1]);
             if (2 * g + 1 < COUT) so[spin_f2(2 * g + 1, k, A.g.ps, scb)] = make_float2(acc[t][2], acc[t][3]);
@@ -625,29 +647,43 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     }
 }
 
+// Split the nine paths of each 64-site group over two waves (the last layer of the learned
+// preconditioner: even outputs only) when the unsplit launch would give the chip at most one
+// round of two waves per SIMD (1024 SIMDs); WD_PTCONV_SPLIT = 0 / 1 forces it off / on.
+static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsamples)
+{
+    if (!(hf && cin == 8 && cout == 4 && A.spin_out && A.out_sites == A.g.Vh && A.zero_par < 0 && nsamples == 1))
+        return false;
+    if (const char* e = getenv("WD_PTCONV_SPLIT")) return atoi(e) != 0;
+    return (A.g.Vh + 63) / 64 <= 2048;
+}
+
 template <int R>
 static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples, bool hf)
 {
-    const int waves = (A.out_sites > A.g.Vh ? 2 : 1) * ((A.g.Vh + 63) / 64);
+    const bool split = ptconv_split(A, hf, cin, cout, nsamples);
+    const int waves = (A.out_sites > A.g.Vh || split ? 2 : 1) * ((A.g.Vh + 63) / 64);
     dim3 grid((waves + 3) / 4, nsamples), block(256);
     const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
-    if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
-        if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, true>), grid, block, 0, ctx->stream, A);
-        else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, true>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true>), grid, block, 0, ctx->stream, A);
+    if (split) {
+        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true, true>), grid, block, 0, ctx->stream, A);
+    } else if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
+        if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, true, false>), grid, block, 0, ctx->stream, A);
+        else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, true, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true, false>), grid, block, 0, ctx->stream, A);
     } else if (cin == 4 && cout == 8) {
-        if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, false>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, false, false, false>), grid, block, 0, ctx->stream, A);
+        if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, false, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, false, false, false, false>), grid, block, 0, ctx->stream, A);
     } else if (cin == 8 && cout == 8) {
-        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, false>), grid, block, 0, ctx->stream, A);
+        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, false, false>), grid, block, 0, ctx->stream, A);
     } else if (cin == 8 && cout == 4) {
-        if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, false>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, false, false>), grid, block, 0, ctx->stream, A);
+        if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, false, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, false, false, false>), grid, block, 0, ctx->stream, A);
     } else {
-        if (si && so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, true, false>), grid, block, 0, ctx->stream, A);
-        else if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, false, false>), grid, block, 0, ctx->stream, A);
-        else if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, true, false>), grid, block, 0, ctx->stream, A);
-        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, false, false>), grid, block, 0, ctx->stream, A);
+        if (si && so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, true, false, false>), grid, block, 0, ctx->stream, A);
+        else if (si) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, true, false, false, false>), grid, block, 0, ctx->stream, A);
+        else if (so) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, true, false, false>), grid, block, 0, ctx->stream, A);
+        else hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 4, false, false, false, false>), grid, block, 0, ctx->stream, A);
     }
     WD_LAUNCHED();
     return WD_OK;

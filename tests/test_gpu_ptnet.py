@@ -9,7 +9,8 @@ bf16; a rounding error of u = 2^-9 at each of five stages stays well below
 1e-2 in the relative L2 norm of the output; the bound is 2e-2.  The bf16 path
 must differ from the float32-feature path (it did round), and the float32-feature
 path with the parity skip must equal the one without it bit for bit (the skipped
-paths add exact zeros)."""
+paths add exact zeros).  The last layer with its paths split over two waves (the
+default on small lattices) and unsplit agree to float32 summation order (1e-5)."""
 import ctypes
 
 import numpy as np
@@ -75,6 +76,12 @@ def test_preconditioner_application_matches_oracle(dims, monkeypatch):
     f_hf, got_hf = _apply(w, ctx, g, lat, Vh, wb, w.BF16, fin)
     err_hf = orc.rel_l2(got_hf, ref)
     assert 1e-6 < err_hf < 2e-2, err_hf
+    # on lattices this small the last layer splits each site group's paths over two waves;
+    # unsplit, the same products are summed in another order (float32 accumulation)
+    monkeypatch.setenv("WD_PTCONV_SPLIT", "0")
+    _, got_one = _apply(w, ctx, g, lat, Vh, wb, w.BF16, fin)
+    monkeypatch.delenv("WD_PTCONV_SPLIT")
+    assert orc.rel_l2(got_one, got_hf) < 1e-5
     # the same with float32 hidden features, with and without the parity skip
     monkeypatch.setenv("WD_PTNET_F32_FEATURES", "1")
     f_32, got_32 = _apply(w, ctx, g, lat, Vh, wb, w.BF16, fin)
