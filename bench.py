@@ -91,7 +91,33 @@ def cpu_baseline(U, psi_e, dims, gpu_out=None):
             "sample": "%d application(s) of the FP64 oracle's Mhat^dag Mhat on the full %dx%dx%dx%d lattice "
                       "(%d even sites), %.2f s each" % (reps, *dims, Vh, dt),
             "one_core": cpu_one_core(),
+            "eo_dslash_fp64_vs_fp32_build": cpu_eo_dslash(U, psi_e, dims),
             "step_rel_l2_vs_oracle": None if gpu_out is None else float(orc.rel_l2(gpu_out, ref))}
+
+
+def cpu_eo_dslash(U, psi_e, dims, reps=3):
+    """The oracle's even-output hopping term D_eo (odd input) on all host cores, from the FP64
+    build and from the single-precision build of the same source (the CPU counterpart of the
+    FP32 operator): median of `reps` calls each, GFLOP/s at 1320 flops per even site."""
+    import numpy as np
+    import oracle as orc
+    Vh = psi_e.shape[0]
+    full = orc.eo_merge(np.zeros_like(psi_e), psi_e, dims)   # the source on the odd sites
+    U32, full32 = U.astype(np.complex64), full.astype(np.complex64)   # converted outside the timing
+    res = {}
+    for name, fn in (("fp64", lambda: orc.dhop(U, full, BC, out_parity=0)),
+                     ("fp32_build", lambda: orc.dhop_fp32(U32, full32, BC, out_parity=0))):
+        fn()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        dt = float(np.median(ts))
+        res[name] = {"gflops": round(Vh * FLOPS_DSLASH / dt / 1e9, 3), "s_median": round(dt, 4)}
+    res.update({"cores": orc.num_threads(), "lattice": list(dims),
+                "sample": "%d calls of D_eo per build on %dx%dx%dx%d" % (reps, *dims)})
+    return res
 
 
 _ONE_CORE = r"""

@@ -46,12 +46,19 @@ _lib = None
 BC_DEFAULT = (1, 1, 1, -1)   # periodic in space, antiperiodic in time
 
 
+_LIB32_PATH = os.path.join(_HERE, "libwref32.so")
+_lib32 = None
+
+
 def build(force=False):
-    """Compile wref.c with gcc (never hipcc) into libwref.so."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
+    """Compile wref.c with gcc (never hipcc) into libwref.so, and the same source in single
+    precision (-DWREF_FP32; timed by the benchmark's CPU baseline, never checked against)
+    into libwref32.so."""
+    for path, extra in ((_LIB_PATH, []), (_LIB32_PATH, ["-DWREF_FP32"])):
+        if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+            tmp = path + ".tmp%d" % os.getpid()
+            subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared"] + extra + ["-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB_PATH
 
 
@@ -70,6 +77,33 @@ def _load():
         lib.wref_num_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def _load32():
+    global _lib32
+    if _lib32 is None:
+        if not os.path.exists(_LIB32_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB32_PATH)
+        p = ctypes.c_void_p
+        lib.wref_dhop.argtypes = [p, p, p, p, p, ctypes.c_int, ctypes.c_int]
+        lib.wref_dhop.restype = None
+        _lib32 = lib
+    return _lib32
+
+
+def dhop_fp32(U, psi, bc=BC_DEFAULT, out_parity=-1):
+    """D_hop psi from the single-precision build of the same source (complex64 in and out):
+    for timing only, as the CPU counterpart of a single-precision operator."""
+    lib = _load32()
+    dims = dims_of_links(U)
+    U = np.ascontiguousarray(U, dtype=np.complex64)
+    psi = np.ascontiguousarray(psi, dtype=np.complex64)
+    out = np.empty_like(psi)
+    d = np.array(dims, dtype=np.int32)
+    b = np.array(bc, dtype=np.int32)
+    lib.wref_dhop(d.ctypes.data, b.ctypes.data, U.ctypes.data, psi.ctypes.data, out.ctypes.data, 0, int(out_parity))
+    return out
 
 
 def num_threads():

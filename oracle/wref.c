@@ -25,6 +25,11 @@
  * output sites of that parity are computed (the rest are set to zero): that is
  * P_out D_hop, the operator restricted to one parity.  out_parity = -1 computes
  * every site.
+ *
+ * Built with -DWREF_FP32 the same source runs in single precision (float
+ * storage and arithmetic, interleaved re, im floats): that build is only timed,
+ * as the CPU counterpart of a single-precision operator, and never checked
+ * against.
  */
 #include <complex.h>
 #include <stddef.h>
@@ -33,7 +38,15 @@
 #include <omp.h>
 #endif
 
+#ifdef WREF_FP32
+typedef float real;
+typedef float complex cplx;
+#define conj_c conjf
+#else
+typedef double real;
 typedef double complex cplx;
+#define conj_c conj
+#endif
 
 /* gamma[mu][row][col] in the DeGrand-Rossi basis. */
 static const cplx GAMMA[4][4][4] = {
@@ -61,7 +74,7 @@ static size_t site_index(const int L[4], const int c[4])
  * Adds  sign * (1 + pm * gamma_mu) W chi  into acc, where chi is the full
  * neighbour spinor and W the 3x3 colour matrix (already daggered if needed).
  */
-static void add_hop(cplx acc[4][3], int mu, double pm, double sign, const cplx W[3][3], const cplx chi[4][3])
+static void add_hop(cplx acc[4][3], int mu, real pm, real sign, const cplx W[3][3], const cplx chi[4][3])
 {
     cplx wchi[4][3];
     for (int s = 0; s < 4; ++s)
@@ -78,7 +91,7 @@ static void add_hop(cplx acc[4][3], int mu, double pm, double sign, const cplx W
         }
 }
 
-void wref_dhop(const int dims[4], const int bc[4], const double* U_, const double* in_, double* out_,
+void wref_dhop(const int dims[4], const int bc[4], const real* U_, const real* in_, real* out_,
                int dagger, int out_parity)
 {
     const cplx* U = (const cplx*)U_;
@@ -86,8 +99,8 @@ void wref_dhop(const int dims[4], const int bc[4], const double* U_, const doubl
     cplx* out = (cplx*)out_;
     const size_t V = (size_t)dims[0] * dims[1] * dims[2] * dims[3];
     /* forward hop projector (1 - g) for D, (1 + g) for D^dagger; backward the opposite */
-    const double pm_fwd = dagger ? 1.0 : -1.0;
-    const double pm_bwd = -pm_fwd;
+    const real pm_fwd = dagger ? 1 : -1;
+    const real pm_bwd = -pm_fwd;
 
 #pragma omp parallel for schedule(static)
     for (int64_t s = 0; s < (int64_t)V; ++s) {
@@ -104,11 +117,11 @@ void wref_dhop(const int dims[4], const int bc[4], const double* U_, const doubl
         for (int mu = 0; mu < 4; ++mu) {
             int f[4] = { c[0], c[1], c[2], c[3] };
             int b[4] = { c[0], c[1], c[2], c[3] };
-            double sf = 1.0, sb = 1.0;
+            real sf = 1, sb = 1;
             f[mu] = c[mu] + 1;
-            if (f[mu] == dims[mu]) { f[mu] = 0; sf = (double)bc[mu]; }
+            if (f[mu] == dims[mu]) { f[mu] = 0; sf = (real)bc[mu]; }
             b[mu] = c[mu] - 1;
-            if (b[mu] < 0) { b[mu] = dims[mu] - 1; sb = (double)bc[mu]; }
+            if (b[mu] < 0) { b[mu] = dims[mu] - 1; sb = (real)bc[mu]; }
             size_t xf = site_index(dims, f), xb = site_index(dims, b);
 
             cplx W[3][3], chi[4][3];
@@ -122,7 +135,7 @@ void wref_dhop(const int dims[4], const int bc[4], const double* U_, const doubl
             /* backward: U_mu(x - mu)^dagger psi(x - mu) */
             const cplx* Ub = U + 9 * ((size_t)mu * V + xb);
             for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) W[i][j] = conj(Ub[3 * j + i]);
+                for (int j = 0; j < 3; ++j) W[i][j] = conj_c(Ub[3 * j + i]);
             for (int sp = 0; sp < 4; ++sp)
                 for (int a = 0; a < 3; ++a) chi[sp][a] = in[12 * xb + 3 * sp + a];
             add_hop(acc, mu, pm_bwd, sb, W, chi);

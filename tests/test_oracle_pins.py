@@ -256,6 +256,18 @@ def test_antiperiodic_time_boundary():
     assert np.abs(diff[1:3]).max() == 0.0
 
 
+def test_single_precision_build_computes_the_same_operator():
+    # the FP32 build of the oracle source (timed by the benchmark only) is the same operator
+    # to float32 rounding, on both output parities
+    dims = (4, 2, 4, 6)
+    U = ls.gauge_field(dims, 0.5, 41)
+    psi = spinor(dims, 42)
+    for par in (0, 1):
+        ref = orc.dhop(U, psi, BC, out_parity=par)
+        got = orc.dhop_fp32(U, psi, BC, out_parity=par).astype(np.complex128)
+        assert 1e-9 < orc.rel_l2(got, ref) < 1e-6
+
+
 # ---------------------------------------------------------------------------
 # even-odd preconditioning (Schur complement)
 # ---------------------------------------------------------------------------
