@@ -190,6 +190,37 @@ SHAPE_SWEEP = ((24, 32, 32, 64), (28, 32, 32, 64), (30, 32, 32, 64), (32, 24, 32
                (32, 32, 28, 64), (32, 32, 32, 56), (28, 28, 28, 56), (32, 32, 32, 64))
 
 
+# algorithmic bytes per even output site of one 12-real EO dslash by storage precision
+# (8 links + input + output; 16-bit: 12 reals x 2 B per link, 24 x 2 B + a 4 B scale per spinor)
+BYTES_BY_PREC = {"f64": 8 * 96 + 192 + 192, "f32": BYTES_DSLASH, "f16": 8 * 24 + 52 + 52, "bf16": 8 * 24 + 52 + 52}
+
+
+def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o):
+    """The EO dslash D_eo (no dagger, no update) at every storage precision on the benchmark's
+    field and source, autotuned: median and minimum of five runs of 100 launches, GFLOP/s at
+    1320 flops per site, algorithmic GB/s and fraction of the HBM peak."""
+    X, Y, Z, T = dims
+    Vh = X * Y * Z * T // 2
+    lat = w.lattice(dims, BC)
+    rows = {}
+    for prec in (w.F64, w.F32, w.F16, w.BF16):
+        name = w.PREC_NAMES[prec]
+        g.prepare(prec)
+        fin = w.pack(ctx, lat, w.ODD, prec, psi_o)
+        fout = w.new_field(lat, w.EVEN, prec)
+        w.wd_autotune_dslash(g.handle, prec, 1, None)
+        med, mn = timed_repeats(lambda: w.wd_dslash(g.handle, w.EVEN, 0, prec, 1, fin.data_ptr(), fout.data_ptr()),
+                                stream, torch)
+        b = BYTES_BY_PREC[name]
+        rows[name] = {"us_median": round(med, 3), "us_min": round(mn, 3),
+                      "gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1), "bytes_per_site": b,
+                      "gbs_algorithmic": round(Vh * b / med / 1e3, 1),
+                      "frac_hbm": round(Vh * b / med / 1e3 / HBM_PEAK_GBS, 4),
+                      "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, 1, 0, 0))}
+        del fin, fout
+    return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12>, D_eo", **rows}
+
+
 def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20, shapes=None):
     """FP32 12-real EO dslash on L^3 x 2L lattices (or the given X x Y x Z x T shapes):
     warm (5 x 100 back-to-back launches, median and minimum) and, where the compulsory
@@ -634,6 +665,12 @@ def main():
           "frac_hbm": round(Vh * BYTES_DSLASH / eo_us / 1e3 / HBM_PEAK_GBS, 4),
           "gbs_naive_no_reuse": round(Vh * (8 * (48 + 96) + 96) / eo_us / 1e3, 1)}
 
+    by_prec = None
+    if not args.no_extras:
+        print("bench: EO dslash at every storage precision", file=sys.stderr, flush=True)
+        by_prec = dslash_by_precision(w, ctx, stream, torch, ls, g, dims,
+                                      ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR))
+
     # achievable ceiling: streaming copy of 2 GiB (read + write bytes counted)
     nbytes = 2 << 30
     src = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
@@ -702,6 +739,7 @@ def main():
         "wall_s_timed": round(wall, 4),
         "dslash_eo": eo,
         "dslash_eo_temporal_gauge": gf,
+        "dslash_eo_by_precision": by_prec,
         "copy_gbs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
         "tuned_launch": tuned,
