@@ -11,7 +11,7 @@ Prints one JSON line with the throughput, the roofline of the dslash kernel
 events on the stream the kernels run on) and the FP64 CPU oracle timed on
 the host on the same operator.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--shape-sweep-only]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--shape-sweep-only] [--precision-sweep-only]
 """
 import argparse
 import json
@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-extras", action="store_true", help="skip the multi-rhs and ragged-batch measurements")
     ap.add_argument("--no-sweep", action="store_true", help="skip the L^3 x 2L volume sweep")
+    ap.add_argument("--precision-sweep-only", action="store_true",
+                    help="only the EO dslash at every storage precision on the benchmark lattice (for counter runs)")
     ap.add_argument("--shape-sweep-only", action="store_true",
                     help="only the EO dslash over lattices one extent short of 32^3 x 64 (for counter runs)")
     ap.add_argument("--tune-cache", default=None,
@@ -606,6 +608,13 @@ def main():
         return
     g = w.Gauge(ctx, dims, BC, w.RECON_12)
     g.upload(U)
+    if args.precision_sweep_only:
+        print(json.dumps({"dslash_eo_by_precision": dslash_by_precision(
+            w, ctx, stream, torch, ls, g, dims, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR))}),
+            flush=True)
+        g.close()
+        ctx.close()
+        return
     g.prepare(w.F32)
     lat = w.lattice(dims, BC)
     fin = w.pack(ctx, lat, w.EVEN, w.F32, psi_e)
