@@ -468,7 +468,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         secs = []
         for rep in range(2):
             fx = torch.zeros_like(fb)
-            prm = w.solver_params(tol=tol, maxiter=2000, sloppy=w.F32, delta=1e-4)
+            prm = w.solver_params(tol=tol, maxiter=2000, sloppy=w.F32, delta=-1.0)   # library default (1e-5)
             info = w.WdSolverInfo()
             w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), 16, nl, wid if nl else None, ptrs if nl else None,
                               net.wprec, fb.data_ptr(), fx.data_ptr(), ctypes.byref(info), ok=(w.WD_OK, w.WD_ENOCONV))
@@ -476,7 +476,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
         d = {k: v for k, v in info.as_dict().items() if k not in ("lambda_min", "lambda_max")}
         d["seconds"] = round(d["seconds"], 5)
         d["seconds_first"] = round(secs[0], 5)
-        d["restart"], d["delta"] = 16, 1e-4
+        d["restart"], d["delta"] = 16, 1e-5
         out[name] = d
     g.close()
     out["network_apply_even"] = network_apply_times(w, ctx, net, dims, reps=20)

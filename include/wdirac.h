@@ -324,7 +324,7 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
  * half of the initial guess is used.  Cycles of at most `restart` iterations
  * run in float32 on rhat = bhat - Mhat x_e (bhat = b_e + kappa D_eo b_o, both in
  * float64) and stop when their residual estimate has fallen by params->delta
- * (> 0; else 1e-4); x_e and rhat are updated in float64 after each cycle until
+ * (> 0; else 1e-5); x_e and rhat are updated in float64 after each cycle until
  * ||rhat|| / ||b|| <= params->tol; then x_o = b_o + kappa D_oe x_e, and the full
  * residual ||b - M x|| / ||b||, recomputed in float64, is reported (it equals
  * ||rhat|| / ||b|| up to rounding).  A NaN or a cycle that reduces the residual

@@ -28,14 +28,14 @@ def env():
     ctx.close()
 
 
-def _solve(w, ctx, g, dims, kappa, net_ws=None, widths=None, wprec=0, restart=16, tol=1e-10):
+def _solve(w, ctx, g, dims, kappa, net_ws=None, widths=None, wprec=0, restart=16, tol=1e-10, delta=1e-4):
     import torch
     lat = w.lattice(dims, BC)
     X, Y, Z, T = dims
     b = ls.gaussian_complex((T, Z, Y, X, 4, 3), 9, ls.STREAM_SPINOR)
     fb = w.pack(ctx, lat, w.FULL, w.F64, b)
     fx = torch.zeros_like(fb)
-    prm = w.solver_params(tol=tol, maxiter=3000, sloppy=w.F32, delta=1e-4)
+    prm = w.solver_params(tol=tol, maxiter=3000, sloppy=w.F32, delta=delta)
     info = w.WdSolverInfo()
     if net_ws is None:
         w.wd_fgmres_solve(g.handle, kappa, ctypes.byref(prm), restart, 0, None, None, w.F32, fb.data_ptr(),
@@ -56,24 +56,26 @@ def orc_links(dims):
     return _LINKS[dims]
 
 
-def test_fgmres_unpreconditioned(env):
+# delta -1: the library's default cycle reduction (1e-5)
+@pytest.mark.parametrize("delta", [1e-4, -1.0])
+def test_fgmres_unpreconditioned(env, delta):
     w, ctx, dims, U, g = env
     _LINKS[dims] = U
-    info, res = _solve(w, ctx, g, dims, 0.1248)
+    info, res = _solve(w, ctx, g, dims, 0.1248, delta=delta)
     assert info.status == w.WD_OK and info.fell_back == 0
     assert res <= 1.05e-10, (res, info.as_dict())
     assert abs(res - info.true_resid_M) < 1e-12
 
 
-@pytest.mark.parametrize("wprec", ["f32", "bf16"])
-def test_fgmres_with_network(env, wprec):
+@pytest.mark.parametrize("wprec,delta", [("f32", 1e-4), ("bf16", 1e-4), ("bf16", -1.0)])
+def test_fgmres_with_network(env, wprec, delta):
     import torch
     from paper_0810_5365_amd import ptconv as pt
     w, ctx, dims, U, g = env
     _LINKS[dims] = U
     net = pt.PTNet((4, 8, 8, 4), w.PREC_BY_NAME[wprec])
     net.init_identity(hop=0.02)
-    info, res = _solve(w, ctx, g, dims, 0.1248, net.storage(), net.widths, net.wprec)
+    info, res = _solve(w, ctx, g, dims, 0.1248, net.storage(), net.widths, net.wprec, delta=delta)
     assert info.status == w.WD_OK
     assert res <= 1.05e-10, (res, info.as_dict())
 
