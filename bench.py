@@ -194,13 +194,15 @@ SHAPE_SWEEP = ((24, 32, 32, 64), (28, 32, 32, 64), (30, 32, 32, 64), (32, 24, 32
 
 # algorithmic bytes per even output site of one 12-real EO dslash by storage precision
 # (8 links + input + output; 16-bit: 12 reals x 2 B per link, 24 x 2 B + a 4 B scale per spinor)
-BYTES_BY_PREC = {"f64": 8 * 96 + 192 + 192, "f32": BYTES_DSLASH, "f16": 8 * 24 + 52 + 52, "bf16": 8 * 24 + 52 + 52}
+BYTES_BY_PREC = {"f64": 8 * 96 + 192 + 192, "f32": BYTES_DSLASH, "f16": 8 * 24 + 52 + 52, "bf16": 8 * 24 + 52 + 52,
+                 "f32_r18": 8 * 72 + 96 + 96}
 
 
-def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o):
+def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None):
     """The EO dslash D_eo (no dagger, no update) at every storage precision on the benchmark's
     field and source, autotuned: median and minimum of five runs of 100 launches, GFLOP/s at
-    1320 flops per site, algorithmic GB/s and fraction of the HBM peak."""
+    1320 flops per site, algorithmic GB/s and fraction of the HBM peak; with the links U also
+    FP32 with 18-real links."""
     X, Y, Z, T = dims
     Vh = X * Y * Z * T // 2
     lat = w.lattice(dims, BC)
@@ -220,7 +222,23 @@ def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o):
                       "frac_hbm": round(Vh * b / med / 1e3 / HBM_PEAK_GBS, 4),
                       "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, 1, 0, 0))}
         del fin, fout
-    return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12>, D_eo", **rows}
+    if U is not None:
+        g18 = w.Gauge(ctx, dims, BC, w.RECON_18)
+        g18.upload(U)
+        g18.prepare(w.F32)
+        fin = w.pack(ctx, lat, w.ODD, w.F32, psi_o)
+        fout = w.new_field(lat, w.EVEN, w.F32)
+        w.wd_autotune_dslash(g18.handle, w.F32, 1, None)
+        med, mn = timed_repeats(lambda: w.wd_dslash(g18.handle, w.EVEN, 0, w.F32, 1, fin.data_ptr(), fout.data_ptr()),
+                                stream, torch)
+        b = BYTES_BY_PREC["f32_r18"]
+        rows["f32_r18"] = {"us_median": round(med, 3), "us_min": round(mn, 3),
+                           "gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1), "bytes_per_site": b,
+                           "gbs_algorithmic": round(Vh * b / med / 1e3, 1),
+                           "frac_hbm": round(Vh * b / med / 1e3 / HBM_PEAK_GBS, 4)}
+        del fin, fout
+        g18.close()
+    return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12> (and F32 r18), D_eo", **rows}
 
 
 def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20, shapes=None):
@@ -610,8 +628,8 @@ def main():
     g.upload(U)
     if args.precision_sweep_only:
         print(json.dumps({"dslash_eo_by_precision": dslash_by_precision(
-            w, ctx, stream, torch, ls, g, dims, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR))}),
-            flush=True)
+            w, ctx, stream, torch, ls, g, dims, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR),
+            U)}), flush=True)
         g.close()
         ctx.close()
         return
@@ -678,7 +696,7 @@ def main():
     if not args.no_extras:
         print("bench: EO dslash at every storage precision", file=sys.stderr, flush=True)
         by_prec = dslash_by_precision(w, ctx, stream, torch, ls, g, dims,
-                                      ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR))
+                                      ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR), U)
 
     # achievable ceiling: streaming copy of 2 GiB (read + write bytes counted)
     nbytes = 2 << 30
