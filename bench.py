@@ -406,10 +406,13 @@ def extras(w, ctx, stream, torch, ls):
         b = ctypes.c_void_p()
         w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
         us = timed(lambda: w.wd_batch_run(b), 50)
+        blk, wpc, pf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        w.wd_batch_shape(b, ctypes.byref(blk), ctypes.byref(wpc), ctypes.byref(pf))
         w.wd_batch_destroy(b)
         out["ragged_batch_%s" % w.PREC_NAMES[prec]] = {
             "lattices": ["%dx%dx%dx%d" % d for d in specs], "even_sites": sites, "launches_per_call": 1,
-            "us_per_call": round(us, 2), "gflops": round(sites * FLOPS_DSLASH / us / 1e3, 1)}
+            "us_per_call": round(us, 2), "gflops": round(sites * FLOPS_DSLASH / us / 1e3, 1),
+            "tuned_shape": {"tile_sites": blk.value, "waves_per_cu": wpc.value, "pf": pf.value}}
         for gi, _, _ in keep:
             gi.close()
     return out

@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 3
+#define WD_ABI_VERSION 4
 
 typedef enum {
     WD_OK = 0,
@@ -288,12 +288,20 @@ typedef struct {
  * each with its own nrhs) as ONE persistent kernel launch in a hipGraph.
  * All items use precision prec.  The batch RETAINS the gauge objects and the
  * in/out pointers: they must stay valid until wd_batch_destroy.  Links are
- * packed at prec during this call.  Synchronous. */
+ * packed at prec during this call.  The launch shape (tile width = workgroup
+ * size 64 / 128 / 256 sites, persistent waves per compute unit 8 / 16 / 24 / 32,
+ * software-pipelined directions or not) is autotuned here: every candidate is
+ * launched on the batch's own buffers and timed (so the outputs are written,
+ * with the batch's result), and the fastest is captured; wd_batch_shape
+ * reports it.  Synchronous. */
 wd_status wd_batch_create(wd_context ctx, int n, const wd_batch_item* items, wd_prec prec, wd_batch* out);
 /* Replay the graph on the context's stream (one kernel launch).  Asynchronous. */
 wd_status wd_batch_run(wd_batch b);
-/* Number of tiles (256 output sites of one rhs) and persistent workgroups. */
+/* Number of tiles (one workgroup's output sites of one rhs) and persistent workgroups. */
 wd_status wd_batch_info(wd_batch b, long long* ntiles, int* grid);
+/* The captured launch shape: tile width (sites = workgroup size), persistent waves
+ * per compute unit, software-pipelined directions (1) or not (0). */
+wd_status wd_batch_shape(wd_batch b, int* block, int* waves_per_cu, int* pf);
 wd_status wd_batch_destroy(wd_batch b);
 
 /* ---- bandwidth reference ----------------------------------------------------- */
@@ -376,7 +384,9 @@ int wd_tune_get_n(wd_context ctx, const char* key, int* out, int n);
 /* ---- environment overrides (measurement and testing; results do not change, except as noted) ----
  * WD_DSLASH_BLOCK, _REMAP, _NT, _PF, _RHS_INNER, _ZB  launch shape of an untuned dslash
  * WD_DSLASH_MFMA = 0 / 1   16-bit multi-rhs dslash off / on the matrix cores, tuned or not
- * WD_BATCH_PF = 1          software-pipelined directions in the persistent batch kernel
+ * WD_BATCH_BLOCK, _WAVES, _PF  force the batch launch shape (tile width 64..256, waves per
+ *                          compute unit, pipelined directions 0 / 1) instead of tuning it
+ * WD_BATCH_TUNE = 0        no batch tuning: 256-site tiles, 24 waves per compute unit
  * WD_PTCONV_MFMA = 0       PT-conv channel mixing on the vector units even with bf16 weights
  * WD_PTCONV_ZB = depth     z-block depth of the matrix-core PT-conv wave order (0: natural)
  * WD_PTCONV_PARITY_SKIP = 0  the network inside FGMRES computes every path and site and

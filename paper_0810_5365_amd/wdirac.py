@@ -97,6 +97,7 @@ _PROTOS = {
     "wd_batch_create": ("status", [_V, _I, _P(WdBatchItem), _I, _P(_V)]),
     "wd_batch_run": ("status", [_V]),
     "wd_batch_info": ("status", [_V, _P(ctypes.c_longlong), _P(_I)]),
+    "wd_batch_shape": ("status", [_V, _P(_I), _P(_I), _P(_I)]),
     "wd_batch_destroy": ("status", [_V]),
     "wd_device_copy": ("status", [_V, _V, _V, _S]),
     "wd_bicgstab_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
@@ -113,7 +114,7 @@ _PROTOS = {
 }
 
 _lib = None
-ABI_VERSION = 3   # the structures above match include/wdirac.h at this version
+ABI_VERSION = 4   # the structures above match include/wdirac.h at this version
 
 
 def _raw():

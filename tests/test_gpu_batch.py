@@ -75,6 +75,8 @@ def _run_batch(w, ctx, specs, prec, replays=3):
     w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
     nt, grid = ctypes.c_longlong(), ctypes.c_int()
     w.wd_batch_info(b, ctypes.byref(nt), ctypes.byref(grid))
+    blk, wpc, pf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    w.wd_batch_shape(b, ctypes.byref(blk), ctypes.byref(wpc), ctypes.byref(pf))
     results = []
     for rep in range(replays):
         for k in keep:
@@ -85,15 +87,17 @@ def _run_batch(w, ctx, specs, prec, replays=3):
         outs = [w.unpack(ctx, k[2], k[6], prec, k[5], k[3].shape, k[9]) for k in keep]
         results.append(outs)
     w.wd_batch_destroy(b)
-    return keep, results, nt.value, grid.value
+    return keep, results, nt.value, grid.value, (blk.value, wpc.value, pf.value)
 
 
 def test_ragged_batch_one_launch_f32(w):
     ctx = w.Context(0)
     specs = [((8, 8, 8, 8), True, 0, 3, 101), ((12, 12, 12, 12), False, 1, 1, 102),
              ((6, 4, 10, 4), True, 1, 2, 103), ((2, 2, 2, 2), False, 0, 1, 104)]
-    keep, results, ntiles, grid = _run_batch(w, ctx, specs, w.F32)
-    expect_tiles = sum(((d[0] * d[1] * d[2] * d[3] // 2 + 255) // 256) * n for d, _, _, n, _ in specs)
+    keep, results, ntiles, grid, shape = _run_batch(w, ctx, specs, w.F32)
+    blk, wpc, pf = shape   # the tuned launch shape
+    assert blk in (64, 128, 256) and wpc in (8, 16, 24, 32) and pf in (0, 1)
+    expect_tiles = sum(((d[0] * d[1] * d[2] * d[3] // 2 + blk - 1) // blk) * n for d, _, _, n, _ in specs)
     assert ntiles == expect_tiles and 1 <= grid <= ntiles
     for outs in results:
         for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
@@ -109,12 +113,35 @@ def test_ragged_batch_one_launch_f32(w):
 def test_ragged_batch_16bit(w, prec):
     ctx = w.Context(0)
     specs = [((8, 8, 8, 8), True, 0, 2, 201), ((12, 12, 12, 12), True, 0, 1, 202), ((4, 6, 2, 10), False, 1, 3, 203)]
-    keep, results, _, _ = _run_batch(w, ctx, specs, w.PREC_BY_NAME[prec], replays=2)
+    keep, results, _, _, _ = _run_batch(w, ctx, specs, w.PREC_BY_NAME[prec], replays=2)
     for outs in results:
         for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
             ref = ref_hop(U, psi, out_even, bool(dagger))
             for r in range(nrhs):
                 assert orc.rel_l2(got[r], ref[r]) < 5e-3
+    for k in keep:
+        k[1].close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("block,waves,pf", [(64, 8, 0), (128, 32, 1), (256, 16, 1), (64, 24, 1)])
+def test_ragged_batch_every_forced_shape(w, monkeypatch, block, waves, pf):
+    """Launch shapes forced through the environment (no tuning): tile widths 64..256, waves
+    per compute unit, pipelined directions; the tile count follows the width."""
+    monkeypatch.setenv("WD_BATCH_BLOCK", str(block))
+    monkeypatch.setenv("WD_BATCH_WAVES", str(waves))
+    monkeypatch.setenv("WD_BATCH_PF", str(pf))
+    ctx = w.Context(0)
+    specs = [((8, 8, 8, 8), True, 0, 2, 301), ((6, 4, 10, 4), False, 1, 3, 302), ((2, 2, 2, 2), True, 1, 1, 303)]
+    keep, results, ntiles, grid, shape = _run_batch(w, ctx, specs, w.F32, replays=2)
+    assert shape == (block, waves, pf)
+    assert ntiles == sum(((d[0] * d[1] * d[2] * d[3] // 2 + block - 1) // block) * n for d, _, _, n, _ in specs)
+    assert 1 <= grid <= ntiles
+    for outs in results:
+        for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
+            ref = ref_hop(U, psi, out_even, bool(dagger))
+            for r in range(nrhs):
+                assert orc.rel_l2(got[r], ref[r]) < 1e-5
     for k in keep:
         k[1].close()
     ctx.close()
@@ -175,7 +202,7 @@ def test_ragged_batch_full_size_lattices(w):
     ctx = w.Context(0)
     specs = [((8, 8, 8, 8), True, 0, 1, 4101), ((12, 12, 12, 12), True, 0, 1, 4102),
              ((16, 16, 16, 32), True, 0, 1, 4103), ((24, 24, 24, 32), True, 0, 1, 4104)]
-    keep, results, _, _ = _run_batch(w, ctx, specs, w.F32, replays=2)
+    keep, results, _, _, _ = _run_batch(w, ctx, specs, w.F32, replays=2)
     for outs in results:
         for (U, g, lat, psi, fin, fout, out_sub, out_even, dagger, nrhs), got in zip(keep, outs):
             assert orc.rel_l2(got[0], ref_hop(U, psi, out_even, False)[0]) < 1e-5
