@@ -338,7 +338,11 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
  * ||rhat|| / ||b|| up to rounding).  A NaN or a cycle that reduces the residual
  * less than tenfold hands x to wd_wilson_solve (fell_back = 1), whose float64
  * residual is reported.
- * restart must be in [1, 63].  Synchronous. */
+ * With BF16 weights of widths 4 -> 8 -> ... -> 8 -> 4 the network keeps its hidden
+ * features in bf16 (see wd_ptnet_apply_even).  restart must be in [1, 63].
+ * WD_EINVAL: a null pointer, restart out of range, tol <= 0, a network not mapping
+ * 4 to 4 channels or a weight precision other than F32 / F16 / BF16;
+ * WD_EUNSUPPORTED: a width outside {1, 2, 3, 4, 8}.  Synchronous. */
 wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* params, int restart, int nlayers,
                           const int* widths, const void* const* weights, wd_prec wprec, const void* b, void* x,
                           wd_solver_info* info);
