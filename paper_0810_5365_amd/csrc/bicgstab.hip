@@ -97,16 +97,10 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         const cd ts(ctx->hres[0], ctx->hres[1]);
         const double tt = ctx->hres[2];
         omega = tt > 0.0 ? ts / tt : cd(0.0);
-        {   // x_s += alpha p + omega s
-            const void* in[3] = {xs, p, s};
-            const double cr[3] = {1.0, alpha.real(), omega.real()}, ci[3] = {0.0, alpha.imag(), omega.imag()};
-            WD_TRY(blas_lincomb(ctx, G, 1, ps, 3, in, cr, ci, xs, nullptr, false));
-        }
-        {   // r = s - omega t, with ||r||^2 and <r0, r> (the next rho)
-            const void* in[2] = {s, t};
-            const double cr[2] = {1.0, -omega.real()}, ci[2] = {0.0, -omega.imag()};
-            WD_TRY(blas_lincomb(ctx, G, 1, ps, 2, in, cr, ci, rs, r0, true));
-        }
+        // x_s += alpha p + omega s and r = s - omega t, with ||r||^2 and <r0, r> (the next rho),
+        // in one sweep
+        WD_TRY(blas_bicg_xr(ctx, G, ps, xs, p, s, t, r0, rs, alpha.real(), alpha.imag(), omega.real(), omega.imag(),
+                            true));
         dirty = true;
         rho = rho_new;
         info->iters++;

@@ -417,6 +417,98 @@ __global__ void __launch_bounds__(RED_BLOCK) lincomb_kernel(Lincomb L, SiteRange
     if constexpr (RED) block_reduce<3>(acc, partials);
 }
 
+// BiCGstab's two closing updates in one sweep over s: xs += alpha p + omega s and
+// r = s - omega t, with ||r||^2 and <r0, r> (values 0, 1, 2), each in the order and with the
+// values lincomb_kernel uses for it alone.
+struct BicgXR {
+    SiteRange Xs, P, S, T, R0, Rs;
+    double ar, ai, wr, wi;
+};
+
+template <int P>
+__global__ void __launch_bounds__(RED_BLOCK) bicg_xr_kernel(BicgXR B, long long nsites, double* partials)
+{
+    using T = typename RealOf<P>::T;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (long long st = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; st < nsites;
+         st += (long long)gridDim.x * RED_BLOCK) {
+        const long long h = st / B.Xs.Vh;
+        const uint32_t cb = (uint32_t)(st - h * B.Xs.Vh);
+        const int ps = B.Xs.ps;
+        T sv[24], o[24], x[24];
+        SpinorIO<P>::load(B.S.half(h), ps, cb, sv);
+        // xs + alpha p + omega s
+#pragma unroll
+        for (int q = 0; q < 24; ++q) o[q] = 0;
+        const T one = (T)1.0, zero = (T)0.0;
+        SpinorIO<P>::load(B.Xs.half(h), ps, cb, x);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            o[2 * q] += one * x[2 * q] - zero * x[2 * q + 1];
+            o[2 * q + 1] += one * x[2 * q + 1] + zero * x[2 * q];
+        }
+        SpinorIO<P>::load(B.P.half(h), ps, cb, x);
+        const T ar = (T)B.ar, ai = (T)B.ai, wr = (T)B.wr, wi = (T)B.wi;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            o[2 * q] += ar * x[2 * q] - ai * x[2 * q + 1];
+            o[2 * q + 1] += ar * x[2 * q + 1] + ai * x[2 * q];
+        }
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            o[2 * q] += wr * sv[2 * q] - wi * sv[2 * q + 1];
+            o[2 * q + 1] += wr * sv[2 * q + 1] + wi * sv[2 * q];
+        }
+        SpinorIO<P>::store((char*)B.Xs.half(h), ps, cb, o);
+        // s - omega t
+#pragma unroll
+        for (int q = 0; q < 24; ++q) o[q] = 0;
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            o[2 * q] += one * sv[2 * q] - zero * sv[2 * q + 1];
+            o[2 * q + 1] += one * sv[2 * q + 1] + zero * sv[2 * q];
+        }
+        SpinorIO<P>::load(B.T.half(h), ps, cb, x);
+        const T mwr = (T)(-B.wr), mwi = (T)(-B.wi);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            o[2 * q] += mwr * x[2 * q] - mwi * x[2 * q + 1];
+            o[2 * q + 1] += mwr * x[2 * q + 1] + mwi * x[2 * q];
+        }
+        SpinorIO<P>::store((char*)B.Rs.half(h), ps, cb, o);
+        SpinorIO<P>::load(B.R0.half(h), ps, cb, x);
+#pragma unroll
+        for (int q = 0; q < 12; ++q) {
+            const double orr = o[2 * q], oi = o[2 * q + 1], rr = x[2 * q], ri = x[2 * q + 1];
+            acc[0] += orr * orr + oi * oi;
+            acc[1] += rr * orr + ri * oi;
+            acc[2] += rr * oi - ri * orr;
+        }
+    }
+    block_reduce<3>(acc, partials);
+}
+
+wd_status blas_bicg_xr(wd_context ctx, const Geom& g, int prec, void* xs, const void* p, const void* s, const void* t,
+                       const void* r0, void* rs, double alpha_re, double alpha_im, double omega_re, double omega_im,
+                       bool fetch)
+{
+    const size_t hb = half_bytes(g, prec);
+    auto R = [&](const void* q) { return SiteRange{(const char*)q, g.Vh, g.ps, hb}; };
+    BicgXR B{R(xs), R(p), R(s), R(t), R(r0), R(rs), alpha_re, alpha_im, omega_re, omega_im};
+    const long long ns = g.Vh;
+    const int nblk = red_blocks(ns);
+    WD_TRY(ensure_reduction(ctx, (size_t)nblk * 3));
+    switch (prec) {
+    case WD_F64: hipLaunchKernelGGL((bicg_xr_kernel<P_F64>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, ns, ctx->partials); break;
+    case WD_F32: hipLaunchKernelGGL((bicg_xr_kernel<P_F32>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, ns, ctx->partials); break;
+    case WD_F16: hipLaunchKernelGGL((bicg_xr_kernel<P_F16>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, ns, ctx->partials); break;
+    case WD_BF16: hipLaunchKernelGGL((bicg_xr_kernel<P_BF16>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, B, ns, ctx->partials); break;
+    default: set_error("bicg_xr: bad precision %d", prec); return WD_EINVAL;
+    }
+    WD_LAUNCHED();
+    return finish(ctx, nblk, 3, fetch);
+}
+
 wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nh, int prec, int n, const void* const* x,
                        const double* cre, const double* cim, void* out, const void* r0, bool fetch)
 {

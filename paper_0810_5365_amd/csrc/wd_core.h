@@ -167,6 +167,11 @@ wd_status reduce_partials(wd_context ctx, int nblk, int n, int slot);
 // ||out||^2 and <r0, out> (dres/hres 0; 1, 2)
 wd_status blas_lincomb(wd_context ctx, const Geom& g, size_t nhalves, int prec, int n, const void* const* x,
                        const double* cre, const double* cim, void* out, const void* r0, bool fetch);
+// one EVEN half each: xs += alpha p + omega s; rs = s - omega t, with ||rs||^2, Re and Im <r0, rs>
+// in slots 0, 1, 2
+wd_status blas_bicg_xr(wd_context ctx, const Geom& g, int prec, void* xs, const void* p, const void* s, const void* t,
+                       const void* r0, void* rs, double alpha_re, double alpha_im, double omega_re, double omega_im,
+                       bool fetch);
 // h_i = <V_i, w> for i < k, V_i = V + i * vstride bytes; complex results in dres[slot + 2i],
 // dres[slot + 2i + 1] (and hres); with_norm adds ||w||^2 in dres[slot + 2k]
 wd_status blas_mdot(wd_context ctx, const Geom& g, size_t nhalves, int prec, const void* V, size_t vstride, int k,
