@@ -308,6 +308,47 @@ def test_eo_schur_solution_matches_sparse_solve(dims):
     assert orc.rel_residual(lambda v: orc.apply_m(U, v, kappa, BC), x, b) < 1e-12
 
 
+@pytest.mark.parametrize("dims", [(2, 2, 2, 4), (4, 2, 2, 4)])
+@pytest.mark.parametrize("parity", [0, 1])
+@pytest.mark.parametrize("dagger", [False, True])
+def test_eo_schur_both_parities_and_daggers_match_sparse_solve(dims, parity, dagger):
+    """Each parity's Schur complement, with and without the dagger, solves the full system.
+
+    Block form of M (or M^dagger) over (even, odd) sites: [[1, -k D_eo], [-k D_oe, 1]].
+    Eliminating the other parity gives, for parity p with partner q,
+        (1 - k^2 D_pq D_qp) x_p = b_p + k D_pq b_q,   x_q = b_q + k D_qp x_p,
+    with every hop daggered for M^dagger.  The reference x is scipy's sparse LU solve of
+    the full lattice system, so a swapped hop order, a kappa power or a dagger slip in the
+    oracle's parity-1 or dagger branch of mhat fails here."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    U = ls.gauge_field(dims, 0.5, 37)
+    kappa = 0.124
+    X, Y, Z, T = dims
+    shape = (T, Z, Y, X, 4, 3)
+    Vh = X * Y * Z * T // 2
+    M = sp.csc_matrix(_dense(lambda v: orc.apply_m(U, v, kappa, BC, dagger=dagger), shape))
+    b = spinor(dims, 11)
+    x_ref = spla.spsolve(M, b.ravel()).reshape(shape)
+    q = 1 - parity
+    hop_pq = orc.d_eo if parity == 0 else orc.d_oe     # q-sites -> p-sites
+    hop_qp = orc.d_oe if parity == 0 else orc.d_eo     # p-sites -> q-sites
+    b_p, b_q = orc.eo_split(b, dims, parity), orc.eo_split(b, dims, q)
+    bh = b_p + kappa * hop_pq(U, b_q, BC, dagger)
+    Mh = _dense(lambda v: orc.mhat(U, v, kappa, BC, dagger=dagger, parity=parity), (Vh, 4, 3))
+    x_p = np.linalg.solve(Mh, bh.ravel()).reshape(Vh, 4, 3)
+    x_q = b_q + kappa * hop_qp(U, x_p, BC, dagger)
+    x = orc.eo_merge(x_p, x_q, dims) if parity == 0 else orc.eo_merge(x_q, x_p, dims)
+    assert orc.rel_l2(x, x_ref) < 1e-12
+    assert orc.rel_residual(lambda v: orc.apply_m(U, v, kappa, BC, dagger=dagger), x, b) < 1e-12
+    if not dagger:
+        # the normal operator of this parity is the product of the two pinned branches
+        Mh_dag = _dense(lambda v: orc.mhat(U, v, kappa, BC, dagger=True, parity=parity), (Vh, 4, 3))
+        assert np.abs(Mh_dag - Mh.conj().T).max() < 1e-13
+        N = _dense(lambda v: orc.mhat_dag_mhat(U, v, kappa, BC, parity), (Vh, 4, 3))
+        assert np.abs(N - Mh.conj().T @ Mh).max() < 1e-12
+
+
 def test_mhat_adjoint_and_normal_operator(rough):
     dims, U = rough
     X, Y, Z, T = dims
