@@ -295,7 +295,12 @@ typedef struct {
  * with the batch's result), and the fastest is captured; wd_batch_shape
  * reports it.  Synchronous. */
 wd_status wd_batch_create(wd_context ctx, int n, const wd_batch_item* items, wd_prec prec, wd_batch* out);
-/* Replay the graph on the context's stream (one kernel launch).  Asynchronous. */
+/* Replay the graph on the context's stream (one kernel launch).  Asynchronous.
+ * The captured launch knows whether each item's links were in temporal gauge at
+ * creation; if a gauge has been uploaded again or fixed since, so that this no
+ * longer holds, nothing is launched and WD_EINVAL is returned (create the batch
+ * again).  Uploading new links of the same state between runs is allowed: the
+ * links are repacked in place. */
 wd_status wd_batch_run(wd_batch b);
 /* Number of tiles (one workgroup's output sites of one rhs) and persistent workgroups. */
 wd_status wd_batch_info(wd_batch b, long long* ntiles, int* grid);

@@ -59,6 +59,9 @@ struct wd_batch_s {
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // each item's gauge and whether its links were in temporal gauge when the launch was
+    // captured (the kernel skips the unit t-links then); a later upload or fix changes that
+    std::vector<std::pair<wd_gauge, bool>> gauge_state;
 };
 
 namespace wd {
@@ -178,6 +181,7 @@ wd_status wd_batch_create(wd_context ctx, int n, const wd_batch_item* items, wd_
     wd_batch b = new wd_batch_s();
     b->ctx = ctx;
     b->nitems = n;
+    for (int i = 0; i < n; ++i) b->gauge_state.emplace_back(items[i].gauge, items[i].gauge->gf);
     auto fail = [&](wd_status s) {
         destroy_batch(b);
         return s;
@@ -278,6 +282,12 @@ wd_status wd_batch_run(wd_batch b)
         set_error("wd_batch_run: NULL batch");
         return WD_EINVAL;
     }
+    for (size_t i = 0; i < b->gauge_state.size(); ++i)
+        if (b->gauge_state[i].first->gf != b->gauge_state[i].second) {
+            set_error("wd_batch_run: item %zu's gauge was %s since the batch was created; create the batch again",
+                      i, b->gauge_state[i].second ? "uploaded again" : "fixed to the temporal gauge");
+            return WD_EINVAL;
+        }
     WD_HIP(hipGraphLaunch(b->exec, b->ctx->stream));
     return WD_OK;
 }

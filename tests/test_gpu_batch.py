@@ -49,17 +49,39 @@ def test_multi_rhs_orderings(w, monkeypatch, rhs_inner):
     ctx.close()
 
 
+_INPUTS = {}
+
+
+def _inputs(dims, seed, nrhs):
+    """Seeded links (eps 0.5) and nrhs input half fields, generated once per module."""
+    key = (dims, seed, nrhs)
+    if key not in _INPUTS:
+        _INPUTS[key] = (ls.gauge_field(dims, 0.5, seed), half_source(dims, seed + 1, nrhs))
+    return _INPUTS[key]
+
+
+_REFS = {}
+
+
+def _ref(spec):
+    """The oracle's hopping term for one batch item (all its rhs), computed once per module."""
+    if spec not in _REFS:
+        dims, out_even, dagger, nrhs, seed = spec
+        U, psi = _inputs(dims, seed, nrhs)
+        _REFS[spec] = ref_hop(U, psi, out_even, bool(dagger))
+    return _REFS[spec]
+
+
 def _run_batch(w, ctx, specs, prec, replays=3):
     """specs: list of (dims, out_even, dagger, nrhs, seed)."""
     import torch
     items = (w.WdBatchItem * len(specs))()
     keep = []
     for i, (dims, out_even, dagger, nrhs, seed) in enumerate(specs):
-        U = ls.gauge_field(dims, 0.5, seed)
+        U, psi = _inputs(dims, seed, nrhs)
         g = w.Gauge(ctx, dims, BC, 12)
         g.upload(U)
         lat = w.lattice(dims, BC)
-        psi = half_source(dims, seed + 1, nrhs)
         in_sub, out_sub = (w.ODD, w.EVEN) if out_even else (w.EVEN, w.ODD)
         fin = w.pack(ctx, lat, in_sub, prec, psi, nrhs)
         fout = w.new_field(lat, out_sub, prec, nrhs)
@@ -208,4 +230,107 @@ def test_ragged_batch_full_size_lattices(w):
             assert orc.rel_l2(got[0], ref_hop(U, psi, out_even, False)[0]) < 1e-5
     for k in keep:
         k[1].close()
+    ctx.close()
+
+
+# The multi-rhs and ragged workload as one batch: 16 Gaussian rhs on 16^3 x 32 together
+# with the lattices 8^4, 12^4, 16^3 x 32 and 24^3 x 32 (eps 0.5), all in one launch.
+C4_SPECS = [((16, 16, 16, 32), True, 0, 16, 4100), ((8, 8, 8, 8), True, 0, 1, 4101),
+            ((12, 12, 12, 12), True, 0, 1, 4102), ((16, 16, 16, 32), True, 0, 1, 4103),
+            ((24, 24, 24, 32), True, 0, 1, 4104)]
+# two small items with ragged tiles, odd outputs and the dagger, appended for the forced shapes
+SMALL_SPECS = [((2, 2, 2, 2), False, 1, 1, 4105), ((6, 4, 10, 4), False, 1, 3, 4106)]
+
+
+def _site_max_err(got, ref):
+    """Largest per-site error norm over the RMS site norm of the reference."""
+    d = np.abs(got - ref).reshape(got.shape[0], -1)
+    r = np.abs(ref).reshape(ref.shape[0], -1)
+    return float(np.sqrt((d * d).sum(1)).max() / np.sqrt((r * r).sum(1).mean()))
+
+
+def _check_items(keep, results, specs, tol, site_tol=None):
+    for outs in results:
+        for spec, k, got in zip(specs, keep, outs):
+            ref = _ref(spec)
+            for r in range(spec[3]):
+                err = orc.rel_l2(got[r], ref[r])
+                assert err < tol, (spec, r, err)
+                if site_tol is not None:
+                    assert _site_max_err(got[r], ref[r]) < site_tol, (spec, r)
+
+
+@pytest.mark.parametrize("block,waves,pf", [(64, 1, 0), (128, 2, 0), (256, 1, 1)])
+def test_persistent_batch_walks_many_tiles_per_workgroup(w, monkeypatch, block, waves, pf):
+    """Forced launch shapes with far fewer persistent workgroups than tiles, so every
+    workgroup walks a range of tiles across item boundaries: the full-size workload
+    (16 rhs on 16^3 x 32 plus the four ragged lattices) and two small items with ragged
+    tiles, odd outputs and the dagger, each rhs checked against the oracle."""
+    monkeypatch.setenv("WD_BATCH_BLOCK", str(block))
+    monkeypatch.setenv("WD_BATCH_WAVES", str(waves))
+    monkeypatch.setenv("WD_BATCH_PF", str(pf))
+    ctx = w.Context(0)
+    specs = C4_SPECS + SMALL_SPECS
+    keep, results, ntiles, grid, shape = _run_batch(w, ctx, specs, w.F32, replays=2)
+    assert shape == (block, waves, pf)
+    assert ntiles == sum(((d[0] * d[1] * d[2] * d[3] // 2 + block - 1) // block) * n for d, _, _, n, _ in specs)
+    assert grid < ntiles and ntiles >= 20 * grid, (ntiles, grid)
+    _check_items(keep, results, specs, 1e-5, site_tol=1e-5)
+    for k in keep:
+        k[1].close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_multi_rhs_and_ragged_lattices_in_one_launch(w, prec):
+    """The 16-rhs item and the four ragged lattices in ONE batch (one graph launch), the
+    launch shape autotuned: every rhs of every item against the oracle (F32 1e-5, BF16
+    storage 5e-3)."""
+    ctx = w.Context(0)
+    p = w.PREC_BY_NAME[prec]
+    keep, results, ntiles, grid, shape = _run_batch(w, ctx, C4_SPECS, p, replays=2)
+    assert 1 <= grid <= ntiles
+    if p == w.F32:
+        _check_items(keep, results, C4_SPECS, 1e-5, site_tol=1e-5)
+    else:
+        _check_items(keep, results, C4_SPECS, 5e-3)
+    for k in keep:
+        k[1].close()
+    ctx.close()
+
+
+def test_batch_run_refuses_a_gauge_whose_temporal_state_changed(w):
+    """A batch captured on plain links must not run on links fixed to the temporal gauge
+    since (the captured kernel would load t-links the fixed field no longer needs, and the
+    reverse would skip links that are not the identity); a re-upload in the captured state
+    is fine."""
+    import torch
+    ctx = w.Context(0)
+    dims = (4, 4, 4, 8)
+    U, psi = _inputs(dims, 4200, 1)
+    g = w.Gauge(ctx, dims, BC, 12)
+    g.upload(U)
+    lat = w.lattice(dims, BC)
+    fin = w.pack(ctx, lat, w.ODD, w.F32, psi, 1)
+    fout = w.new_field(lat, w.EVEN, w.F32, 1)
+    items = (w.WdBatchItem * 1)()
+    items[0].gauge, items[0].out_subset, items[0].dagger, items[0].nrhs = g.handle.value, w.EVEN, 0, 1
+    items[0].in_, items[0].out = fin.data_ptr(), fout.data_ptr()
+    b = ctypes.c_void_p()
+    w.wd_batch_create(ctx.handle, 1, items, w.F32, ctypes.byref(b))
+    lib = w._raw()
+    U2 = ls.gauge_field(dims, 0.5, 4201)
+    g.upload(U2)                                   # same (unfixed) state: runs, on the new links
+    assert lib.wd_batch_run(b) == w.WD_OK
+    torch.cuda.synchronize()
+    got = w.unpack(ctx, lat, w.EVEN, w.F32, fout, psi.shape, 1)
+    assert orc.rel_l2(got[0], orc.d_eo(U2, psi[0], BC)) < 1e-5
+    w.wd_gauge_fix_temporal(g.handle, None)
+    fout.fill_(7)
+    assert lib.wd_batch_run(b) == w.WD_EINVAL      # state changed: refused, nothing written
+    assert b"create the batch again" in lib.wd_last_error()
+    torch.cuda.synchronize()
+    assert int((fout != 7).sum()) == 0
+    w.wd_batch_destroy(b)
+    g.close()
     ctx.close()
