@@ -107,8 +107,15 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         double rr_s = ctx->hres[0];
         rho_new = cd(ctx->hres[1], ctx->hres[2]);
         have_rho = true;
-        if (!std::isfinite(rr_s) || std::abs(omega) == 0.0) {
-            set_error("BiCGstab breakdown at iteration %d", info->iters);
+        if (!std::isfinite(rr_s)) {
+            set_error("BiCGstab: non-finite residual at iteration %d", info->iters);
+            status = WD_ENAN;
+            break;
+        }
+        // omega = 0 with a converged s (t = Mhat s = 0) is no breakdown: r = s is the
+        // residual, and the float64 check below decides
+        if (std::abs(omega) == 0.0 && rr_s > target) {
+            set_error("BiCGstab breakdown: omega = 0 at iteration %d", info->iters);
             status = WD_ENAN;
             break;
         }
@@ -134,7 +141,11 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         WD_TRY(true_res(&rr));
     }
     info->true_resid = std::sqrt(rr / bnorm2);
-    if (status != WD_ENAN) status = rr <= target ? WD_OK : WD_ENOCONV;
+    // the recomputed float64 residual decides: converged is WD_OK even after a breakdown
+    // (the iterate it left may already meet tol), non-finite is WD_ENAN
+    if (std::isfinite(rr) && rr <= target) status = WD_OK;
+    else if (status == WD_ENAN || !std::isfinite(rr)) status = WD_ENAN;
+    else status = WD_ENOCONV;
     return status;
 }
 
@@ -173,6 +184,13 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
     const double bb = ctx->hres[0];
     wd_status s = WD_OK;
+    if (!std::isfinite(bb)) {   // NaN or Inf in the source: nothing to iterate on
+        set_error("wd_bicgstab_solve: the source holds NaN or Inf");
+        info->true_resid = info->true_resid_M = bb;
+        info->status = WD_ENAN;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        return WD_ENAN;
+    }
     if (bb > 0.0) {
         s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info);
         if (s != WD_OK && s != WD_ENOCONV) return s;

@@ -113,6 +113,11 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     info->cycles = 0;
     info->fell_back = 0;
     *fallback = false;
+    if (!std::isfinite(bb)) {   // NaN or Inf in the source: nothing to iterate on, no fallback
+        set_error("wd_fgmres_solve: the source holds NaN or Inf");
+        info->true_resid = info->true_resid_M = bb;
+        return WD_ENAN;
+    }
     if (!(bb > 0.0)) {
         WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
         info->true_resid = info->true_resid_M = 0.0;

@@ -118,12 +118,19 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     const double target_w = tol2 * P.wnorm2;
     *info = wd_solver_info{};
     std::vector<double> alphas, betas;   // for the Ritz-value estimates
+    if (!std::isfinite(cc)) {   // NaN or Inf in the source: x is left as it was
+        set_error("CG: the right-hand side holds NaN or Inf");
+        info->true_resid = cc;
+        info->true_resid_M = P.bhat ? cc : -1.0;
+        info->status = WD_ENAN;
+        return WD_ENAN;
+    }
     if (!(cc > 0.0)) {
         WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
         info->true_resid = 0.0;
         info->true_resid_M = P.bhat ? 0.0 : -1.0;
-        info->status = std::isfinite(cc) ? WD_OK : WD_ENAN;
-        return (wd_status)info->status;
+        info->status = WD_OK;
+        return WD_OK;
     }
 
     double rr, ww;
