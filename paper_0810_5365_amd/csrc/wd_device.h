@@ -111,8 +111,13 @@ template <> __device__ __forceinline__ float h2f<P_BF16>(uint32_t b)
     return __uint_as_float(b << 16);
 }
 template <int P> __device__ __forceinline__ uint32_t f2h(float f);
+// The codec rounds a float32 value.  Left alone, the compiler folds a caller's product
+// v * inv into the conversion (one mixed-precision FMA rounds the exact product straight
+// to 16 bits), which differs from rounding the float32 product about once in 2^14 values;
+// an empty register constraint makes the operand a float32 register value first.
 template <> __device__ __forceinline__ uint32_t f2h<P_F16>(float f)
 {
+    asm("" : "+v"(f));
     return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)f);
 }
 template <> __device__ __forceinline__ uint32_t f2h<P_BF16>(float f)
@@ -133,9 +138,15 @@ template <int P> __device__ __forceinline__ uint32_t pack2(float a, float b)
 {
     return f2h<P>(a) | (f2h<P>(b) << 16);
 }
-// bf16 pairs: gfx950 converts two floats with round-to-nearest-even in one instruction
+// bf16 and f16 pairs: gfx950 converts two floats with round-to-nearest-even in one instruction
 typedef __bf16 wd_bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 wd_f16x2 __attribute__((ext_vector_type(2)));
 typedef float wd_f32x2 __attribute__((ext_vector_type(2)));
+template <> __device__ __forceinline__ uint32_t pack2<P_F16>(float a, float b)
+{
+    asm("" : "+v"(a), "+v"(b));   // float32 operands, as in f2h<P_F16>
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(wd_f32x2{a, b}, wd_f16x2));
+}
 template <> __device__ __forceinline__ uint32_t pack2<P_BF16>(float a, float b)
 {
     return __builtin_bit_cast(uint32_t, __builtin_convertvector(wd_f32x2{a, b}, wd_bf16x2));
