@@ -200,6 +200,21 @@ wd_status wd_dot(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_pre
                  const void* a, const void* b, double* result);
 wd_status wd_norm2(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
                    const void* a, double* result);
+/* <a, b> with no allocation of any kind, for callers that cannot allocate device
+ * memory (code under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the result of wd_dot, bit for bit, on the CURRENT HIP device and on
+ * `stream` (a hipStream_t, NULL for the null stream), with no context.
+ * Scratch: the per-workgroup partial sums and the two final values live in a static
+ * device array of 2 * 2048 + 2 doubles (32.8 KB) that every GPU the library runs on
+ * holds until the process ends.  The reduction grid is capped at 2048 workgroups, so
+ * fields of every size the library accepts fit it; there is no separate size limit.
+ * All calls on one GPU share that array: calls that overlap in time on one GPU (from
+ * several host threads or streams) race and must be serialised by the caller.
+ * a, b: packed device fields (layout of wd_spinor_bytes); result: host, 2 doubles.
+ * Synchronises `stream`.  WD_EINVAL: NULL pointer, bad subset, precision or nrhs, or a
+ * current device index of 64 or more; WD_ESHAPE: bad lattice; WD_EHIP: a HIP failure. */
+wd_status wd_dot_noalloc(void* stream, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                         const void* a, const void* b, double* result);
 /* y = alpha * x + y with complex alpha = (alpha_re, alpha_im); F32 and F64 only. */
 wd_status wd_caxpy(wd_context ctx, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
                    double alpha_re, double alpha_im, const void* x, void* y);

@@ -7,6 +7,7 @@
 // subset shares one code path.  Reductions are deterministic: a fixed grid of
 // workgroups each reduces a fixed strided set of sites (wave shuffles, then
 // LDS), and one workgroup sums the partials in a fixed order.
+#include <mutex>
 #include <type_traits>
 
 #include "wd_core.h"
@@ -784,4 +785,94 @@ extern "C" wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, 
         return WD_EINVAL;
     }
     return wd::launch_copy(ctx, src, dst, bytes);
+}
+
+// ---- the global sum <a, b> with no allocation anywhere ---------------------------------
+// For callers that cannot allocate device memory (code under stream capture, tight serving
+// loops, harnesses that forbid it): the per-workgroup partial sums and the two final values
+// live in a file-scope device array, one copy per GPU, held until the process ends.  Host
+// code never passes `scratch` itself to a kernel (in host code the name is a host-side
+// stand-in); it looks up each device's address once, with that device current, and passes
+// that address.  Every call on one GPU shares its copy: calls that overlap in time on one GPU
+// (two host threads, or two streams) race, and must be serialised by the caller.  Nothing
+// needs clearing: every call writes all the partials it reads.
+namespace wd {
+
+constexpr int NOALLOC_SLOTS = 2 * RED_MAXBLOCKS + 2;   // two partial rows, then Re and Im
+static __device__ __align__(256) double scratch[NOALLOC_SLOTS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mu;
+static double* noalloc_ptr[NOALLOC_MAX_DEVICES];   // scratch's address on each device, once known
+
+static wd_status noalloc_scratch(int device, double** out)
+{
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        set_error("wd_dot_noalloc: device %d beyond the %d supported", device, NOALLOC_MAX_DEVICES);
+        return WD_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(noalloc_mu);
+    if (!noalloc_ptr[device]) {   // the current device is `device`
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error("wd_dot_noalloc: hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                      hipGetErrorString(e));
+            return WD_EHIP;
+        }
+        noalloc_ptr[device] = (double*)p;
+    }
+    *out = noalloc_ptr[device];
+    return WD_OK;
+}
+
+template <int P>
+static wd_status dot_noalloc_t(hipStream_t stream, const Geom& g, size_t nh, const void* a, const void* b,
+                               double* dev_scratch)
+{
+    const long long n = (long long)nh * g.Vh;
+    const int nblk = red_blocks(n);
+    if (2 * nblk + 2 > NOALLOC_SLOTS) {   // red_blocks caps the grid, so this never fires
+        set_error("wd_dot_noalloc: %d workgroups exceed the scratch array", nblk);
+        return WD_EINVAL;
+    }
+    SiteRange A{(const char*)a, g.Vh, g.ps, half_bytes(g, P)}, B{(const char*)b, g.Vh, g.ps, half_bytes(g, P)};
+    hipLaunchKernelGGL((dot_kernel<P, true>), dim3(nblk), dim3(RED_BLOCK), 0, stream, A, B, n, dev_scratch);
+    WD_LAUNCHED();
+    double* res = dev_scratch + 2 * RED_MAXBLOCKS;
+    hipLaunchKernelGGL(finish_kernel, dim3(2), dim3(RED_BLOCK), 0, stream, dev_scratch, nblk, res, (double*)nullptr);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+} // namespace wd
+
+extern "C" wd_status wd_dot_noalloc(void* stream, const wd_lattice* lat, wd_subset subset, wd_prec prec, int nrhs,
+                                    const void* a, const void* b, double* result)
+{
+    using namespace wd;
+    if (!a || !b || !result) {
+        set_error("wd_dot_noalloc: NULL argument");
+        return WD_EINVAL;
+    }
+    if (!valid_subset(subset) || !valid_prec(prec) || nrhs < 1 || nrhs > 65535) {
+        set_error("wd_dot_noalloc: bad subset %d, precision %d or nrhs %d", (int)subset, (int)prec, nrhs);
+        return WD_EINVAL;
+    }
+    Geom g;
+    WD_TRY(make_geom(lat, &g));
+    int device = 0;
+    WD_HIP(hipGetDevice(&device));
+    double* s = nullptr;
+    WD_TRY(noalloc_scratch(device, &s));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t nh = halves_of(subset, nrhs);
+    switch (prec) {
+    case WD_F64: WD_TRY(dot_noalloc_t<P_F64>(st, g, nh, a, b, s)); break;
+    case WD_F32: WD_TRY(dot_noalloc_t<P_F32>(st, g, nh, a, b, s)); break;
+    case WD_F16: WD_TRY(dot_noalloc_t<P_F16>(st, g, nh, a, b, s)); break;
+    case WD_BF16: WD_TRY(dot_noalloc_t<P_BF16>(st, g, nh, a, b, s)); break;
+    }
+    WD_HIP(hipMemcpyAsync(result, s + 2 * RED_MAXBLOCKS, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    WD_HIP(hipStreamSynchronize(st));
+    return WD_OK;
 }

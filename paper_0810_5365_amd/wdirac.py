@@ -84,6 +84,7 @@ _PROTOS = {
     "wd_apply_MdagM": ("status", [_V, _D, _I, _I, _I, _V, _V]),
     "wd_dot": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V, _P(_D)]),
     "wd_norm2": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _P(_D)]),
+    "wd_dot_noalloc": ("status", [_V, _P(WdLattice), _I, _I, _I, _V, _V, _P(_D)]),
     "wd_caxpy": ("status", [_V, _P(WdLattice), _I, _I, _I, _D, _D, _V, _V]),
     "wd_cg_solve": ("status", [_V, _D, _I, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
     "wd_wilson_solve": ("status", [_V, _D, _P(WdSolverParams), _V, _V, _P(WdSolverInfo)]),
