@@ -55,7 +55,9 @@ def kernel_source_sha():
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_0810_5365_amd", "csrc")
-    for f in ("dslash_body.h", "dslash.hip", "wd_device.h"):
+    # everything that shapes the timed launches: the kernel body, its launcher, device helpers,
+    # the host core, the tuner that picks the launch shapes, and the step's composition
+    for f in ("dslash_body.h", "dslash.hip", "wd_device.h", "wd_core.h", "tune.hip", "api.hip"):
         h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()
 
@@ -241,16 +243,38 @@ def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None):
     return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12> (and F32 r18), D_eo", **rows}
 
 
-def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), mall_bytes=256 << 20, shapes=None):
-    """FP32 12-real EO dslash on L^3 x 2L lattices (or the given X x Y x Z x T shapes):
-    warm (5 x 100 back-to-back launches, median and minimum) and, where the compulsory
-    working set fits the 256 MB last-level cache, single launches timed alone, warm and
-    cold (after 1 GiB of other traffic).  The links are the sub-box of the 32^3 x 64
-    field: i.i.d. per link, so each is a field of the same distribution."""
+def single_launch_us(run, stream, torch, cold, n=20):
+    """One launch at a time between events (median and minimum over n, microseconds):
+    warm = right after another launch of the same call, so whatever of its working set the
+    caches kept is still there; cold = after evicting it with a 1 GiB write and then a
+    1 GiB read of other buffers (so that no dirty line of the write is still being written
+    back when the launch starts)."""
     import numpy as np
-    scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
-    scrub2 = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+    if cold:
+        scrub = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        scrub2 = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t = []
+    for _ in range(n):
+        if cold:
+            scrub.fill_(1)
+            scrub2.sum()
+        else:
+            run()
+        e0.record(stream)
+        run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t.append(e0.elapsed_time(e1) * 1e3)
+    return float(np.median(t)), float(min(t))
+
+
+def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32), shapes=None):
+    """FP32 12-real EO dslash on L^3 x 2L lattices (or the given X x Y x Z x T shapes):
+    warm (5 x 100 back-to-back launches, median and minimum) and single launches timed
+    alone, warm and cold (after 1 GiB of other traffic).  The links are the sub-box of the
+    32^3 x 64 field: i.i.d. per link, so each is a field of the same distribution."""
+    import numpy as np
     rows = []
     for dims in (shapes if shapes is not None else [(L, L, L, 2 * L) for L in sizes]):
         X, Y, Z, T = dims
@@ -275,32 +299,14 @@ def volume_sweep(w, ctx, stream, torch, ls, U, sizes=(8, 12, 16, 20, 24, 28, 32)
                "tuned": w.tune_get(ctx, w.dslash_key(dims, w.F32, 12, 1, 0, 0))}
         if shapes is None:
             row["L"] = X
-        if ws < mall_bytes:
-            # one launch at a time between events: first with the data left in the caches by
-            # the previous launch, then after evicting it (a 1 GiB write, then a 1 GiB read so
-            # that no dirty lines of the write are still being written back)
-            single = {}
-            for mode in ("warm_single", "cold"):
-                t = []
-                for _ in range(20):
-                    if mode == "cold":
-                        scrub.fill_(1)
-                        scrub2.sum()
-                    else:
-                        run()
-                    e0.record(stream)
-                    run()
-                    e1.record(stream)
-                    torch.cuda.synchronize()
-                    t.append(e0.elapsed_time(e1) * 1e3)
-                single[mode] = float(np.median(t))
-                row.update({mode + "_us_median": round(single[mode], 3), mode + "_us_min": round(min(t), 3)})
-            row.update({"cold_gflops": round(Vh * FLOPS_DSLASH / single["cold"] / 1e3, 1),
-                        "cold_frac_hbm": round(ws / single["cold"] / 1e3 / HBM_PEAK_GBS, 4)})
+            for mode, cold in (("warm_single", False), ("cold", True)):
+                med1, mn1 = single_launch_us(run, stream, torch, cold)
+                row.update({mode + "_us_median": round(med1, 3), mode + "_us_min": round(mn1, 3)})
+            row.update({"cold_gflops": round(Vh * FLOPS_DSLASH / row["cold_us_median"] / 1e3, 1),
+                        "cold_frac_hbm": round(ws / row["cold_us_median"] / 1e3 / HBM_PEAK_GBS, 4)})
         rows.append(row)
         del fin, fout
         g.close()
-    del scrub, scrub2
     return {"kernel": "dslash_kernel<F32, r12>, autotuned per lattice", "bytes_per_site": BYTES_DSLASH, "rows": rows}
 
 
@@ -387,34 +393,47 @@ def extras(w, ctx, stream, torch, ls):
         out["multi_rhs_16c32_%s" % name] = rec
     g.close()
 
-    specs = [(8, 8, 8, 8), (12, 12, 12, 12), (16, 16, 16, 32), (24, 24, 24, 32)]
-    for prec in (w.F32, w.BF16):
-        items = (w.WdBatchItem * len(specs))()
-        keep = []
-        sites = 0
-        for i, d in enumerate(specs):
-            gi = w.Gauge(ctx, d, BC, 12)
-            gi.upload(ls.gauge_field(d, 0.5, ls.link_seed(4, i + 1)))
-            li = w.lattice(d, BC)
-            vh = d[0] * d[1] * d[2] * d[3] // 2
-            fi = w.pack(ctx, li, w.ODD, prec, ls.gaussian_complex((vh, 4, 3), ls.source_seed(4, i + 1), ls.STREAM_SPINOR))
-            fo = w.new_field(li, w.EVEN, prec)
-            items[i].gauge, items[i].out_subset, items[i].dagger, items[i].nrhs = gi.handle.value, w.EVEN, 0, 1
-            items[i].in_, items[i].out = fi.data_ptr(), fo.data_ptr()
-            keep.append((gi, fi, fo))
-            sites += vh
-        b = ctypes.c_void_p()
-        w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
-        us = timed(lambda: w.wd_batch_run(b), 50)
-        blk, wpc, pf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
-        w.wd_batch_shape(b, ctypes.byref(blk), ctypes.byref(wpc), ctypes.byref(pf))
-        w.wd_batch_destroy(b)
-        out["ragged_batch_%s" % w.PREC_NAMES[prec]] = {
-            "lattices": ["%dx%dx%dx%d" % d for d in specs], "even_sites": sites, "launches_per_call": 1,
-            "us_per_call": round(us, 2), "gflops": round(sites * FLOPS_DSLASH / us / 1e3, 1),
-            "tuned_shape": {"tile_sites": blk.value, "waves_per_cu": wpc.value, "pf": pf.value}}
-        for gi, _, _ in keep:
-            gi.close()
+    # the ragged lattices alone, then together with the 16-rhs item in the same single launch
+    ragged = [((8, 8, 8, 8), 1), ((12, 12, 12, 12), 1), ((16, 16, 16, 32), 1), ((24, 24, 24, 32), 1)]
+    for name, specs in (("ragged_batch", ragged), ("multi_rhs_and_ragged_one_launch", [((16, 16, 16, 32), 16)] + ragged)):
+        for prec in (w.F32, w.BF16):
+            items = (w.WdBatchItem * len(specs))()
+            keep = []
+            sites = site_rhs = nbytes = 0
+            link_b, spin_b = (48, 96) if prec == w.F32 else (24, 52)
+            for i, (d, nr) in enumerate(specs):
+                gi = w.Gauge(ctx, d, BC, 12)
+                seed = ls.link_seed(4, i + 1) if nr == 1 else ls.link_seed(4)
+                gi.upload(ls.gauge_field(d, 0.5, seed))
+                li = w.lattice(d, BC)
+                vh = d[0] * d[1] * d[2] * d[3] // 2
+                src = ls.gaussian_complex((nr, vh, 4, 3), ls.source_seed(4, i + 1) if nr == 1 else ls.source_seed(4),
+                                          ls.STREAM_SPINOR)
+                fi = w.pack(ctx, li, w.ODD, prec, src, nr)
+                fo = w.new_field(li, w.EVEN, prec, nr)
+                items[i].gauge, items[i].out_subset, items[i].dagger, items[i].nrhs = gi.handle.value, w.EVEN, 0, nr
+                items[i].in_, items[i].out = fi.data_ptr(), fo.data_ptr()
+                keep.append((gi, fi, fo))
+                sites += vh
+                site_rhs += vh * nr
+                nbytes += vh * 8 * link_b + vh * nr * 2 * spin_b   # links once per site, spinors per rhs
+            b = ctypes.c_void_p()
+            w.wd_batch_create(ctx.handle, len(specs), items, prec, ctypes.byref(b))
+            us = timed(lambda: w.wd_batch_run(b), 50)
+            blk, wpc, pf = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            w.wd_batch_shape(b, ctypes.byref(blk), ctypes.byref(wpc), ctypes.byref(pf))
+            nt, grid = ctypes.c_longlong(), ctypes.c_int()
+            w.wd_batch_info(b, ctypes.byref(nt), ctypes.byref(grid))
+            w.wd_batch_destroy(b)
+            out["%s_%s" % (name, w.PREC_NAMES[prec])] = {
+                "items": ["%dx%dx%dx%d x %d rhs" % (d + (nr,)) for d, nr in specs], "even_sites": sites,
+                "site_rhs": site_rhs, "launches_per_call": 1, "us_per_call": round(us, 2),
+                "gflops": round(site_rhs * FLOPS_DSLASH / us / 1e3, 1), "algorithmic_mb": round(nbytes / 1e6, 1),
+                "gbs_algorithmic": round(nbytes / us / 1e3, 1), "frac_hbm": round(nbytes / us / 1e3 / HBM_PEAK_GBS, 4),
+                "tiles": nt.value, "persistent_workgroups": grid.value,
+                "tuned_shape": {"tile_sites": blk.value, "waves_per_cu": wpc.value, "pf": pf.value}}
+            for gi, _, _ in keep:
+                gi.close()
     return out
 
 
@@ -689,10 +708,16 @@ def main():
     eo_us = e0.elapsed_time(e1) * 1e3 / n_eo
     eo_med, eo_min = timed_repeats(lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fodd.data_ptr(), fout.data_ptr()),
                                    stream, torch)
+    eo_run = lambda: w.wd_dslash(g.handle, w.EVEN, 0, w.F32, 1, fodd.data_ptr(), fout.data_ptr())
+    cold_med, cold_min = single_launch_us(eo_run, stream, torch, cold=True)
     eo = {"us_per_launch": round(eo_us, 3), "us_median_5x100": round(eo_med, 3), "us_min_5x100": round(eo_min, 3),
+          "timing": "warm: back-to-back repeats on the same buffers (the 256 MB last-level cache keeps part "
+                    "of the 604 MB working set between repeats); cold: one launch after 1 GiB of other traffic",
           "gflops": round(Vh * FLOPS_DSLASH / eo_us / 1e3, 1),
           "gbs_algorithmic": round(Vh * BYTES_DSLASH / eo_us / 1e3, 1),
           "frac_hbm": round(Vh * BYTES_DSLASH / eo_us / 1e3 / HBM_PEAK_GBS, 4),
+          "cold_us_median": round(cold_med, 3), "cold_us_min": round(cold_min, 3),
+          "cold_frac_hbm": round(Vh * BYTES_DSLASH / cold_med / 1e3 / HBM_PEAK_GBS, 4),
           "gbs_naive_no_reuse": round(Vh * (8 * (48 + 96) + 96) / eo_us / 1e3, 1)}
 
     by_prec = None

@@ -44,7 +44,8 @@ def _load():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        # LATTICE_SYNTH_LIB names another build of synth.c to load instead (the sanitizer test's)
+        lib = ctypes.CDLL(os.environ.get("LATTICE_SYNTH_LIB") or _LIB_PATH)
         u64, u32, dbl = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
         ptr = ctypes.c_void_p
         lib.ls_gaussian.argtypes = [u64, u64, u32, dbl, ptr]

@@ -40,6 +40,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wref.c")
+# ORACLE_WREF_LIB / ORACLE_WREF32_LIB name other builds of wref.c to load instead (the
+# sanitizer test's)
 _LIB_PATH = os.path.join(_HERE, "libwref.so")
 _lib = None
 
@@ -62,12 +64,14 @@ def build(force=False):
     return _LIB_PATH
 
 
+# ORACLE_WREF_LIB / ORACLE_WREF32_LIB name other builds of wref.c to load instead of the two
+# built here (the sanitizer test's).
 def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(os.environ.get("ORACLE_WREF_LIB") or _LIB_PATH)
         p = ctypes.c_void_p
         lib.wref_dhop.argtypes = [p, p, p, p, p, ctypes.c_int, ctypes.c_int]
         lib.wref_dhop.restype = None
@@ -84,7 +88,7 @@ def _load32():
     if _lib32 is None:
         if not os.path.exists(_LIB32_PATH):
             build()
-        lib = ctypes.CDLL(_LIB32_PATH)
+        lib = ctypes.CDLL(os.environ.get("ORACLE_WREF32_LIB") or _LIB32_PATH)
         p = ctypes.c_void_p
         lib.wref_dhop.argtypes = [p, p, p, p, p, ctypes.c_int, ctypes.c_int]
         lib.wref_dhop.restype = None

@@ -108,8 +108,12 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     WD_TRY(ws_get(ctx, "cg.rs", half_bytes(G, pacc) * nh, &rs));
     WD_TRY(ws_get(ctx, "cg.xs", half_bytes(G, pacc) * nh, &xs));
     WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &p));
-    WD_TRY(ws_get(ctx, "cg.ap", half_bytes(G, pop) * nh, &ap));
+    // on one parity A p = Mhat^dag (Mhat p) is formed in place of Mhat p (the fused update of
+    // Mhat^dag reads x at the site it writes), so the iteration touches one field fewer and
+    // more of its fields stay in the last-level cache; on the full lattice it cannot be
+    if (P.subset == WD_FULL) WD_TRY(ws_get(ctx, "cg.ap", half_bytes(G, pop) * nh, &ap));
     WD_TRY(ws_get(ctx, "cg.mp", half_bytes(G, pop) * nh, &mp));
+    if (P.subset != WD_FULL) ap = mp;
 
     WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
     const double cc = ctx->hres[0];
