@@ -12,6 +12,7 @@ events on the stream the kernels run on) and the FP64 CPU oracle timed on
 the host on the same operator.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--shape-sweep-only] [--precision-sweep-only]
+                    [--multi-rhs-only]
 """
 import argparse
 import json
@@ -46,6 +47,8 @@ def parse():
                     help="only the EO dslash at every storage precision on the benchmark lattice (for counter runs)")
     ap.add_argument("--shape-sweep-only", action="store_true",
                     help="only the EO dslash over lattices one extent short of 32^3 x 64 (for counter runs)")
+    ap.add_argument("--multi-rhs-only", action="store_true",
+                    help="only the 16-rhs records on 16^3 x 32 (per-rhs and matrix-core paths; for counter runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning table: loaded if it exists (no tuning), else tuned and written there")
     return ap.parse_args()
@@ -197,10 +200,10 @@ SHAPE_SWEEP = ((24, 32, 32, 64), (28, 32, 32, 64), (30, 32, 32, 64), (32, 24, 32
 # algorithmic bytes per even output site of one 12-real EO dslash by storage precision
 # (8 links + input + output; 16-bit: 12 reals x 2 B per link, 24 x 2 B + a 4 B scale per spinor)
 BYTES_BY_PREC = {"f64": 8 * 96 + 192 + 192, "f32": BYTES_DSLASH, "f16": 8 * 24 + 52 + 52, "bf16": 8 * 24 + 52 + 52,
-                 "f32_r18": 8 * 72 + 96 + 96}
+                 "f32_r18": 8 * 72 + 96 + 96, "f16_r18": 8 * 36 + 52 + 52, "bf16_r18": 8 * 36 + 52 + 52}
 
 
-def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None):
+def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None, tune=True):
     """The EO dslash D_eo (no dagger, no update) at every storage precision on the benchmark's
     field and source, autotuned: median and minimum of five runs of 100 launches, GFLOP/s at
     1320 flops per site, algorithmic GB/s and fraction of the HBM peak; with the links U also
@@ -214,7 +217,8 @@ def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None):
         g.prepare(prec)
         fin = w.pack(ctx, lat, w.ODD, prec, psi_o)
         fout = w.new_field(lat, w.EVEN, prec)
-        w.wd_autotune_dslash(g.handle, prec, 1, None)
+        if tune:
+            w.wd_autotune_dslash(g.handle, prec, 1, None)
         med, mn = timed_repeats(lambda: w.wd_dslash(g.handle, w.EVEN, 0, prec, 1, fin.data_ptr(), fout.data_ptr()),
                                 stream, torch)
         b = BYTES_BY_PREC[name]
@@ -225,22 +229,27 @@ def dslash_by_precision(w, ctx, stream, torch, ls, g, dims, psi_o, U=None):
                       "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 12, 1, 0, 0))}
         del fin, fout
     if U is not None:
+        # 18-real links: no row rebuild, 50% more link bytes
         g18 = w.Gauge(ctx, dims, BC, w.RECON_18)
         g18.upload(U)
-        g18.prepare(w.F32)
-        fin = w.pack(ctx, lat, w.ODD, w.F32, psi_o)
-        fout = w.new_field(lat, w.EVEN, w.F32)
-        w.wd_autotune_dslash(g18.handle, w.F32, 1, None)
-        med, mn = timed_repeats(lambda: w.wd_dslash(g18.handle, w.EVEN, 0, w.F32, 1, fin.data_ptr(), fout.data_ptr()),
-                                stream, torch)
-        b = BYTES_BY_PREC["f32_r18"]
-        rows["f32_r18"] = {"us_median": round(med, 3), "us_min": round(mn, 3),
-                           "gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1), "bytes_per_site": b,
-                           "gbs_algorithmic": round(Vh * b / med / 1e3, 1),
-                           "frac_hbm": round(Vh * b / med / 1e3 / HBM_PEAK_GBS, 4)}
-        del fin, fout
+        for prec in (w.F32, w.F16, w.BF16):
+            name = w.PREC_NAMES[prec] + "_r18"
+            g18.prepare(prec)
+            fin = w.pack(ctx, lat, w.ODD, prec, psi_o)
+            fout = w.new_field(lat, w.EVEN, prec)
+            if tune:
+                w.wd_autotune_dslash(g18.handle, prec, 1, None)
+            med, mn = timed_repeats(lambda: w.wd_dslash(g18.handle, w.EVEN, 0, prec, 1, fin.data_ptr(), fout.data_ptr()),
+                                    stream, torch)
+            b = BYTES_BY_PREC[name]
+            rows[name] = {"us_median": round(med, 3), "us_min": round(mn, 3),
+                          "gflops": round(Vh * FLOPS_DSLASH / med / 1e3, 1), "bytes_per_site": b,
+                          "gbs_algorithmic": round(Vh * b / med / 1e3, 1),
+                          "frac_hbm": round(Vh * b / med / 1e3 / HBM_PEAK_GBS, 4),
+                          "tuned": w.tune_get(ctx, w.dslash_key(dims, prec, 18, 1, 0, 0))}
+            del fin, fout
         g18.close()
-    return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12> (and F32 r18), D_eo", **rows}
+    return {"lattice": list(dims), "kernel": "dslash_kernel<P, r12> and <P, r18>, D_eo", **rows}
 
 
 def single_launch_us(run, stream, torch, cold, n=20):
@@ -347,24 +356,10 @@ def slab_extras(w, ctx, stream, torch, ls, U, nslab=8, link_gbs=153.0):
             "modelled_transfer_us_per_direction": round(face / (link_gbs * 1e3), 2)}
 
 
-def extras(w, ctx, stream, torch, ls):
-    """Multi-rhs (16 rhs on 16^3 x 32) and the ragged batch (8^4, 12^4, 16^3 x 32,
-    24^3 x 32 in one persistent graph launch): time per call and GFLOP/s."""
-    import ctypes
+def multi_rhs_records(w, ctx, ls, timed):
+    """16 rhs on 16^3 x 32, FP32 and BF16, tuned: one launch against one launch per rhs, and
+    for BF16 the matrix-core path against the per-rhs kernel."""
     out = {}
-
-    def timed(fn, n):
-        for _ in range(3):
-            fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(n):
-            fn()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) * 1e3 / n
-
     dims, nrhs = (16, 16, 16, 32), 16
     Vh = 16 * 16 * 16 * 32 // 2
     g = w.Gauge(ctx, dims, BC, 12)
@@ -392,6 +387,30 @@ def extras(w, ctx, stream, torch, ls):
             del os.environ["WD_DSLASH_MFMA"]
         out["multi_rhs_16c32_%s" % name] = rec
     g.close()
+    return out
+
+
+def extras(w, ctx, stream, torch, ls, multi_rhs_only=False):
+    """Multi-rhs (16 rhs on 16^3 x 32) and the ragged batch (8^4, 12^4, 16^3 x 32,
+    24^3 x 32 in one persistent graph launch): time per call and GFLOP/s."""
+    import ctypes
+    out = {}
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    out.update(multi_rhs_records(w, ctx, ls, timed))
+    if multi_rhs_only:
+        return out
 
     # the ragged lattices alone, then together with the 16-rhs item in the same single launch
     ragged = [((8, 8, 8, 8), 1), ((12, 12, 12, 12), 1), ((16, 16, 16, 32), 1), ((24, 24, 24, 32), 1)]
@@ -630,6 +649,18 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream(0)
     ctx = w.Context(0, stream.cuda_stream)
+    if args.multi_rhs_only:
+        rec = extras(w, ctx, stream, torch, ls, multi_rhs_only=True)
+        # a 2 GiB copy (read and write), the reference for hardware byte counters in the same run
+        src = torch.ones(1 << 31, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            w.wd_device_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), 1 << 31)
+        torch.cuda.synchronize()
+        del src, dst
+        print(json.dumps({"multi_rhs": rec}), flush=True)
+        ctx.close()
+        return
 
     print("bench: generating %s links and source" % (dims,), file=sys.stderr, flush=True)
     U = ls.gauge_field(dims, EPS, ls.link_seed(2))
@@ -649,9 +680,17 @@ def main():
     g = w.Gauge(ctx, dims, BC, w.RECON_12)
     g.upload(U)
     if args.precision_sweep_only:
-        print(json.dumps({"dslash_eo_by_precision": dslash_by_precision(
-            w, ctx, stream, torch, ls, g, dims, ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR),
-            U)}), flush=True)
+        # with --tune-cache: the launch shapes of an earlier run are loaded (so that counter runs
+        # under a profiler time the same configurations), else tuned and saved there
+        have = bool(args.tune_cache) and os.path.exists(args.tune_cache)
+        if have:
+            w.wd_tune_load(ctx.handle, args.tune_cache.encode())
+        rec = dslash_by_precision(w, ctx, stream, torch, ls, g, dims,
+                                  ls.gaussian_complex((Vh, 4, 3), ls.source_seed(2, 1), ls.STREAM_SPINOR), U,
+                                  tune=not have)
+        if args.tune_cache and not have:
+            w.wd_tune_save(ctx.handle, args.tune_cache.encode())
+        print(json.dumps({"dslash_eo_by_precision": rec}), flush=True)
         g.close()
         ctx.close()
         return

@@ -259,7 +259,9 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
 /* Solve M x = b on the full lattice through the even-odd Schur complement:
  * b'_e = b_e + kappa D_eo b_o, CG on Mhat^dagger Mhat x_e = Mhat^dagger b'_e,
  * x_o = b_o + kappa D_oe x_e.  b, x: FULL float64 packed fields.  Reports
- * ||b - M x|| / ||b|| in true_resid_M.  Synchronous. */
+ * ||b - M x|| / ||b|| in true_resid_M, evaluated in float64 on the even rows
+ * (b_e - x_e + kappa D_eo x_o, with the x_o built); the odd rows are zero by the
+ * construction of x_o, up to its float64 rounding.  Synchronous. */
 wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
                           const void* b, void* x, wd_solver_info* info);
 
@@ -336,7 +338,8 @@ wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t byte
  * or 16-bit with the per-site scale; arithmetic in float32, float64 for F64);
  * reliable updates recompute bhat - Mhat x in float64 when the iterated
  * residual drops below delta times its running maximum.  true_resid is ||bhat - Mhat x_e|| / ||b||,
- * true_resid_M the full-system ||b - M x|| / ||b||.  Synchronous. */
+ * true_resid_M the full-system ||b - M x|| / ||b|| (float64, even rows evaluated as
+ * for wd_wilson_solve).  Synchronous. */
 wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
                             wd_solver_info* info);
 

@@ -183,6 +183,48 @@ wd_status hop_half(wd_gauge g, int prec, int par, int dagger, int nrhs, const vo
                          half_call(g, links, prec, par, dagger, nrhs, in, in_stride, out, out_stride, x, x_stride, a, b));
 }
 
+// precision of the field a fused reduction stores
+static int red_out_prec(int red, int prec)
+{
+    if (red == RED_RESLO) return WD_F32;
+    if (red == RED_CGR) return prec == WD_F64 ? WD_F64 : WD_F32;
+    return prec;
+}
+
+wd_status op_M_red_partials(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out,
+                            int red, const void* y, const double* coef, int* nblk)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    const long long hb = (long long)half_bytes(G, prec);
+    const long long hbo = (long long)half_bytes(G, red_out_prec(red, prec));
+    const void* links = nullptr;
+    WD_TRY(gauge_links(g, prec, &links));
+    WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
+    if (red_values(red) != 1) {
+        set_error("fused reduction %d: more than one value per workgroup", red);
+        return WD_EUNSUPPORTED;
+    }
+    if (subset == WD_FULL) {   // out_p = in_p - kappa D in_{1-p} for both parities, their sums side by side
+        int n[2] = {0, 0};
+        for (int par = 0; par < 2; ++par) {
+            const char* yp = y ? (const char*)y + par * hb : nullptr;
+            WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, (const char*)in + (1 - par) * hb,
+                                                       2 * hb, (char*)out + par * hbo, 2 * hbo,
+                                                       (const char*)in + par * hb, 2 * hb, 1.0, -kappa),
+                                     red, yp, ctx->partials + n[0], &n[par], coef));
+        }
+        *nblk = n[0] + n[1];
+        return WD_OK;
+    }
+    void* tmp = nullptr;
+    WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
+    const int par = subset == WD_EVEN ? 0 : 1;
+    WD_TRY(hop_half(g, prec, 1 - par, dagger, 1, in, hb, tmp, hb, nullptr, 0, 0.0, 1.0));
+    return launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, tmp, hb, out, hbo, in, hb, 1.0,
+                                               -kappa * kappa), red, y, ctx->partials, nblk, coef);
+}
+
 wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out, int red,
                    const void* y, int slot)
 {
@@ -192,20 +234,10 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, c
     const void* links = nullptr;
     WD_TRY(gauge_links(g, prec, &links));
     WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
-    if (subset == WD_FULL) {   // out_p = in_p - kappa D in_{1-p} for both parities, their sums side by side
-        if (red_values(red) != 1) {
-            set_error("fused reduction %d: not built for the full lattice", red);
-            return WD_EUNSUPPORTED;
-        }
-        int n[2] = {0, 0};
-        for (int par = 0; par < 2; ++par) {
-            const char* yp = y ? (const char*)y + par * hb : nullptr;
-            WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, (const char*)in + (1 - par) * hb,
-                                                       2 * hb, (char*)out + par * hb, 2 * hb,
-                                                       (const char*)in + par * hb, 2 * hb, 1.0, -kappa),
-                                     red, yp, ctx->partials + n[0], &n[par]));
-        }
-        return reduce_partials(ctx, n[0] + n[1], 1, slot);
+    if (subset == WD_FULL || red_values(red) == 1) {
+        int n = 0;
+        WD_TRY(op_M_red_partials(g, kappa, subset, dagger, prec, in, out, red, y, nullptr, &n));
+        return reduce_partials(ctx, n, 1, slot);
     }
     void* tmp = nullptr;
     WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
@@ -215,6 +247,31 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, c
     WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, tmp, hb, out, hb, in, hb, 1.0,
                                                -kappa * kappa), red, y, ctx->partials, &n));
     return reduce_partials(ctx, n, red_values(red), slot);
+}
+
+wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr)
+{
+    wd_context ctx = g->ctx;
+    const Geom& G = g->geom;
+    const long long hb = (long long)half_bytes(G, WD_F64), h32 = (long long)half_bytes(G, WD_F32);
+    const char* b_e = (const char*)b;
+    char* x_e = (char*)x;
+    const void* links = nullptr;
+    WD_TRY(gauge_links(g, WD_F64, &links));
+    WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
+    // x_o = b_o + kappa D_oe x_e
+    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_e + hb, hb, b_e + hb, hb, 1.0, kappa));
+    // the even rows of b - M x: b_e - (x_e - kappa D_eo x_o), summed in float64 (the residual
+    // itself is kept only in float32)
+    void* t = nullptr;
+    WD_TRY(ws_get(ctx, "eo_finish.r", (size_t)h32, &t));
+    int n = 0;
+    WD_TRY(launch_dslash_red(ctx, G, half_call(g, links, WD_F64, 0, 0, 1, x_e + hb, hb, t, h32, x_e, hb, 1.0, -kappa),
+                             RED_RESLO, b_e, ctx->partials, &n));
+    WD_TRY(reduce_partials(ctx, n, 1, 0));
+    WD_TRY(fetch_results(ctx, 1));
+    *rr = ctx->hres[0];
+    return WD_OK;
 }
 
 wd_status op_dslash(wd_gauge g, int subset, int dagger, int prec, int nrhs, const void* in, void* out, const void* x,

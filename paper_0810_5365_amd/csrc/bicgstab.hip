@@ -177,7 +177,6 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     const char* b_e = (const char*)b;
     const char* b_o = b_e + hb;
     char* x_e = (char*)x;
-    char* x_o = x_e + hb;
     void* bhat;
     WD_TRY(ws_get(ctx, "bicg.bhat", hb, &bhat));
     WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, hb, bhat, hb, b_e, hb, 1.0, kappa));
@@ -197,12 +196,9 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     } else {
         WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
     }
-    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
-    void* r;
-    WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
-    WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
-    WD_TRY(fetch_results(ctx, 1));
-    info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
+    double rr_full;
+    WD_TRY(eo_finish(g, kappa, b, x, &rr_full));   // x_o, then ||b - M x||^2 in float64
+    info->true_resid_M = bb > 0 ? std::sqrt(rr_full / bb) : 0.0;
     info->operator_applies++;
     info->status = s;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

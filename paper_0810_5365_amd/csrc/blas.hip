@@ -7,6 +7,9 @@
 // subset shares one code path.  Reductions are deterministic: a fixed grid of
 // workgroups each reduces a fixed strided set of sites (wave shuffles, then
 // LDS), and one workgroup sums the partials in a fixed order.
+#include <atomic>
+#include <chrono>
+#include <cstdint>
 #include <mutex>
 #include <type_traits>
 
@@ -278,96 +281,170 @@ wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nh, int px, const voi
     return WD_EINVAL;
 }
 
-// ---- fused CG steps ------------------------------------------------------------------
-// x += alpha p ; r -= alpha Ap ; partial ||r||^2
-template <int PA, int PO>
-__global__ void __launch_bounds__(RED_BLOCK) cg_xr_kernel(SiteRange X, SiteRange R, SiteRange Pp, SiteRange AP,
-                                                          long long nsites, double alpha, double* partials)
+// ---- CG steps with their coefficients on the device ----------------------------------
+// The CG scalars live in dres[CG_SLOT + ...] (CG_RR the current sloppy ||r||^2, CG_PAP, CG_ALPHA,
+// CG_RRNEW, CG_BETA): the step length is formed on the device by the sum that produces <p, A p>
+// and read there by the launch that updates r, so no host round trip sits between the two
+// operator applications of an iteration.
+static_assert(CG_SLOT + CG_NSLOTS <= 256, "CG scalars past the end of dres");
+
+// mode 0: pap = the sum, alpha = rr / pap.  mode 1: rr_new = the sum, beta = rr_new / rr, and
+// rr_new becomes rr.  The sum goes to the host copy as well.
+__global__ void __launch_bounds__(RED_BLOCK) cg_coef_kernel(const double* __restrict__ partials, int nblk,
+                                                            double* __restrict__ cg, double* __restrict__ host_cg,
+                                                            int mode)
 {
-    using T = typename RealOf<PA>::T;
-    double acc[1] = {0.0};
-    const T al = (T)alpha;
-    for (long long k = (long long)blockIdx.x * RED_BLOCK + threadIdx.x; k < nsites; k += (long long)gridDim.x * RED_BLOCK) {
-        const long long h = k / X.Vh;
-        const uint32_t cb = (uint32_t)(k - h * X.Vh);
-        T x[24], r[24];
-        typename RealOf<PO>::T p[24], ap[24];
-        SpinorIO<PO>::load(Pp.half(h), X.ps, cb, p);
-        SpinorIO<PO>::load(AP.half(h), X.ps, cb, ap);
-        SpinorIO<PA>::load(X.half(h), X.ps, cb, x);
-        SpinorIO<PA>::load(R.half(h), X.ps, cb, r);
-#pragma unroll
-        for (int i = 0; i < 24; ++i) {
-            x[i] += al * (T)p[i];
-            r[i] -= al * (T)ap[i];
-            acc[0] += (double)r[i] * (double)r[i];
+    __shared__ double lds[RED_BLOCK / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nblk; i += RED_BLOCK) s += partials[i];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < RED_BLOCK / 64; ++w) t += lds[w];
+        if (mode == 0) {
+            cg[CG_PAP] = t;
+            cg[CG_ALPHA] = cg[CG_RR] / t;
+            if (host_cg) host_cg[CG_PAP] = t;
+        } else {
+            cg[CG_RRNEW] = t;
+            cg[CG_BETA] = t / cg[CG_RR];
+            cg[CG_RR] = t;
+            if (host_cg) host_cg[CG_RRNEW] = t;
         }
-        SpinorIO<PA>::store((char*)X.half(h), X.ps, cb, x);
-        SpinorIO<PA>::store((char*)R.half(h), X.ps, cb, r);
     }
-    block_reduce<1>(acc, partials);
 }
 
-// p = r + beta p
-template <int PA, int PO>
-__global__ void cg_p_kernel(SiteRange R, SiteRange Pp, long long n, double beta)
+__global__ void cg_set_kernel(double* cg, double rr, double beta)
+{
+    if (threadIdx.x == 0) {
+        cg[CG_RR] = rr;
+        cg[CG_BETA] = beta;
+    }
+}
+
+wd_status blas_cg_coef(wd_context ctx, int nblk, int mode)
+{
+    double* host = ctx->hres_dev ? ctx->hres_dev + CG_SLOT : nullptr;
+    hipLaunchKernelGGL(cg_coef_kernel, dim3(1), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk,
+                       ctx->dres + CG_SLOT, host, mode);
+    WD_LAUNCHED();
+    if (!ctx->hres_dev) {
+        const int k = mode == 0 ? CG_PAP : CG_RRNEW;
+        WD_HIP(hipMemcpyAsync(ctx->hres + CG_SLOT + k, ctx->dres + CG_SLOT + k, sizeof(double), hipMemcpyDeviceToHost,
+                              ctx->stream));
+    }
+    return WD_OK;
+}
+
+// The host arms the two slots it waits for with a NaN payload that no arithmetic produces; the
+// coefficient kernels overwrite them in the mapped host buffer, and the host spins on them
+// instead of synchronising the stream (a stream or event wait would also write the whole L2
+// back to memory, several microseconds per iteration).
+constexpr uint64_t CG_PENDING = 0x7ff4c0ffee000001ull;
+
+void blas_cg_arm(wd_context ctx)
+{
+    if (!ctx->hres_dev) return;
+    volatile uint64_t* h = (volatile uint64_t*)(ctx->hres + CG_SLOT);
+    h[CG_PAP] = CG_PENDING;
+    h[CG_RRNEW] = CG_PENDING;
+}
+
+wd_status blas_cg_wait(wd_context ctx)
+{
+    if (!ctx->hres_dev) {   // the copies were queued behind the kernels
+        WD_HIP(hipStreamSynchronize(ctx->stream));
+        return WD_OK;
+    }
+    volatile uint64_t* h = (volatile uint64_t*)(ctx->hres + CG_SLOT);
+    auto last = std::chrono::steady_clock::now();
+    for (unsigned spins = 1;; ++spins) {
+        if (h[CG_PAP] != CG_PENDING && h[CG_RRNEW] != CG_PENDING) break;
+        // every 2 ms (a query takes the runtime's locks, so not more often): a stream that has
+        // drained without writing them is an error
+        if ((spins & 255u) == 0 && std::chrono::steady_clock::now() - last > std::chrono::milliseconds(2)) {
+            last = std::chrono::steady_clock::now();
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) {
+                if (h[CG_PAP] != CG_PENDING && h[CG_RRNEW] != CG_PENDING) break;
+                set_error("CG: the stream finished without writing its coefficients");
+                return WD_EHIP;
+            }
+            if (e != hipErrorNotReady) {
+                set_error("HIP error while waiting for the CG coefficients: %s", hipGetErrorString(e));
+                return WD_EHIP;
+            }
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return WD_OK;
+}
+
+wd_status blas_cg_set(wd_context ctx, double rr, double beta)
+{
+    hipLaunchKernelGGL(cg_set_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->dres + CG_SLOT, rr, beta);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
+// x += alpha p (XM 0), x = alpha p (XM 1) or x untouched (XM 2); then q = r + beta p (q may be
+// p).  x and r at the accumulation precision PA, p and q at the operator's PO; alpha and beta
+// read on the device.
+template <int PA, int PO, int XM>
+__global__ void cg_xp_kernel(SiteRange X, SiteRange R, SiteRange Pp, char* q, long long n, const double* __restrict__ cg)
 {
     WD_SITE_LOOP(n, R.Vh)
     using T = typename RealOf<PA>::T;
     T r[24];
     typename RealOf<PO>::T p[24];
+    SpinorIO<PO>::load(Pp.half(h), Pp.ps, cb, p);
     SpinorIO<PA>::load(R.half(h), R.ps, cb, r);
-    SpinorIO<PO>::load(Pp.half(h), R.ps, cb, p);
-    const T be = (T)beta;
+    const T al = (T)cg[CG_ALPHA], be = (T)cg[CG_BETA];
+    if constexpr (XM != 2) {
+        T x[24];
+        if constexpr (XM == 0) SpinorIO<PA>::load(X.half(h), X.ps, cb, x);
+#pragma unroll
+        for (int i = 0; i < 24; ++i) x[i] = XM == 0 ? x[i] + al * (T)p[i] : al * (T)p[i];
+        SpinorIO<PA>::store((char*)X.half(h), X.ps, cb, x);
+    }
 #pragma unroll
     for (int i = 0; i < 24; ++i) p[i] = (typename RealOf<PO>::T)(r[i] + be * (T)p[i]);
-    SpinorIO<PO>::store((char*)Pp.half(h), R.ps, cb, p);
+    SpinorIO<PO>::store(q + (size_t)h * Pp.hb, Pp.ps, cb, p);
 }
 
 template <int PA, int PO>
-static wd_status cg_t(wd_context ctx, const Geom& g, size_t nh, void* x, void* r, const void* p, const void* ap, double alpha,
-                      bool fetch)
+static wd_status cg_xp_t(wd_context ctx, long long n, SiteRange X, SiteRange R, SiteRange Pp, char* q, int xmode)
 {
-    const long long n = (long long)nh * g.Vh;
-    const int nblk = red_blocks(n);
-    WD_TRY(ensure_reduction(ctx, (size_t)nblk));
-    const size_t ha = half_bytes(g, PA), ho = half_bytes(g, PO);
-    SiteRange X{(const char*)x, g.Vh, g.ps, ha}, R{(const char*)r, g.Vh, g.ps, ha}, Pp{(const char*)p, g.Vh, g.ps, ho}, AP{(const char*)ap, g.Vh, g.ps, ho};
-    hipLaunchKernelGGL((cg_xr_kernel<PA, PO>), dim3(nblk), dim3(RED_BLOCK), 0, ctx->stream, X, R, Pp, AP, n, alpha,
-                       ctx->partials);
-    WD_LAUNCHED();
-    return finish(ctx, nblk, 1, fetch);
-}
-
-wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nh, int pacc, void* x, void* r, int pop, const void* p,
-                     const void* ap, double alpha, bool fetch)
-{
-    if (pacc == WD_F64 && pop == WD_F64) return cg_t<P_F64, P_F64>(ctx, g, nh, x, r, p, ap, alpha, fetch);
-    if (pacc == WD_F32 && pop == WD_F32) return cg_t<P_F32, P_F32>(ctx, g, nh, x, r, p, ap, alpha, fetch);
-    if (pacc == WD_F32 && pop == WD_F16) return cg_t<P_F32, P_F16>(ctx, g, nh, x, r, p, ap, alpha, fetch);
-    if (pacc == WD_F32 && pop == WD_BF16) return cg_t<P_F32, P_BF16>(ctx, g, nh, x, r, p, ap, alpha, fetch);
-    set_error("cg_xr: unsupported precision pair (%d, %d)", pacc, pop);
-    return WD_EUNSUPPORTED;
-}
-
-wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nh, int pacc, const void* r, int pop, void* p, double beta)
-{
-    const long long n = (long long)nh * g.Vh;
-    SiteRange R{(const char*)r, g.Vh, g.ps, half_bytes(g, pacc)}, Pp{(const char*)p, g.Vh, g.ps, half_bytes(g, pop)};
-    if (pacc == WD_F64 && pop == WD_F64)
-        hipLaunchKernelGGL((cg_p_kernel<P_F64, P_F64>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
-    else if (pacc == WD_F32 && pop == WD_F32)
-        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_F32>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
-    else if (pacc == WD_F32 && pop == WD_F16)
-        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_F16>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
-    else if (pacc == WD_F32 && pop == WD_BF16)
-        hipLaunchKernelGGL((cg_p_kernel<P_F32, P_BF16>), site_grid(n), dim3(256), 0, ctx->stream, R, Pp, n, beta);
-    else {
-        set_error("cg_p: unsupported precision pair (%d, %d)", pacc, pop);
-        return WD_EUNSUPPORTED;
+    const double* cg = ctx->dres + CG_SLOT;
+    switch (xmode) {
+    case 0: hipLaunchKernelGGL((cg_xp_kernel<PA, PO, 0>), site_grid(n), dim3(256), 0, ctx->stream, X, R, Pp, q, n, cg); break;
+    case 1: hipLaunchKernelGGL((cg_xp_kernel<PA, PO, 1>), site_grid(n), dim3(256), 0, ctx->stream, X, R, Pp, q, n, cg); break;
+    default: hipLaunchKernelGGL((cg_xp_kernel<PA, PO, 2>), site_grid(n), dim3(256), 0, ctx->stream, X, R, Pp, q, n, cg); break;
     }
     WD_LAUNCHED();
     return WD_OK;
+}
+
+wd_status blas_cg_xp(wd_context ctx, const Geom& g, size_t nh, int pacc, void* x, int xmode, const void* r, int pop,
+                     const void* p, void* q)
+{
+    const long long n = (long long)nh * g.Vh;
+    SiteRange X{(const char*)x, g.Vh, g.ps, half_bytes(g, pacc)}, R{(const char*)r, g.Vh, g.ps, half_bytes(g, pacc)},
+        Pp{(const char*)p, g.Vh, g.ps, half_bytes(g, pop)};
+    if (xmode < 0 || xmode > 2) {
+        set_error("cg_xp: bad mode %d", xmode);
+        return WD_EINVAL;
+    }
+    char* qc = (char*)q;
+    if (pacc == WD_F64 && pop == WD_F64) return cg_xp_t<P_F64, P_F64>(ctx, n, X, R, Pp, qc, xmode);
+    if (pacc == WD_F32 && pop == WD_F32) return cg_xp_t<P_F32, P_F32>(ctx, n, X, R, Pp, qc, xmode);
+    if (pacc == WD_F32 && pop == WD_F16) return cg_xp_t<P_F32, P_F16>(ctx, n, X, R, Pp, qc, xmode);
+    if (pacc == WD_F32 && pop == WD_BF16) return cg_xp_t<P_F32, P_BF16>(ctx, n, X, R, Pp, qc, xmode);
+    set_error("cg_xp: unsupported precision pair (%d, %d)", pacc, pop);
+    return WD_EUNSUPPORTED;
 }
 
 // ---- fused linear combinations (BiCGstab) ------------------------------------------------

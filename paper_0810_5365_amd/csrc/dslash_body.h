@@ -43,6 +43,7 @@ struct DslashArgs {
     FastDiv dzb, dt; // division by zb and by T for the blocked traversal
     double* red;     // per-workgroup partial sums of a fused reduction (dslash_red.hip)
     const char* y;   // the other operand of the fused <y, out>
+    const double* coef;   // RED_CGR: the step length alpha, in device memory
 };
 
 // Kernel arguments for a launch of the hopping term with launch shape tp (dslash.hip).
@@ -67,6 +68,8 @@ template <int P> __device__ __forceinline__ void quant_roundtrip(float* v)
 //   RED_YDOT  <y, out> (y = A.y), |out|^2    -> r[0] + i r[1], r[2]
 //   RED_RESID out = y - (a x + b D in), |out|^2 -> r[0]   (a residual, stored instead)
 //   RED_YDIFF |y - out|^2                    -> r[0]
+//   RED_RESLO as RED_RESID, the residual stored in float32 -> r[0]
+//   RED_CGR   r -= alpha out (r = A.out at the accumulation precision), |r|^2 -> r[0]
 template <typename T>
 __device__ __forceinline__ void site_dot_norm(const T* a, const T* b, const T* o, double* r)
 {
@@ -223,6 +226,41 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
     } else {
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] *= b;
+    }
+    if constexpr (RED == RED_CGR) {
+        // r -= alpha (a x + b D in) at the accumulation precision; the operator's own result
+        // is never stored
+        constexpr int PA = P == P_F64 ? P_F64 : P_F32;
+        using TA = typename RealOf<PA>::T;
+        char* rp = A.out + rhs * A.out_stride;
+        TA rv[24];
+        SpinorIO<PA>::load(rp, A.g.ps, cb, rv);
+        const TA al = (TA)A.coef[0];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            rv[k] -= al * (TA)acc[k];
+            s += (double)rv[k] * (double)rv[k];
+        }
+        SpinorIO<PA>::store(rp, A.g.ps, cb, rv);
+        red[0] = s;
+        return;
+    }
+    if constexpr (RED == RED_RESLO) {
+        // the float64 residual y - (a x + b D in), its norm taken before it is stored in float32
+        T yv[24];
+        float lo[24];
+        SpinorIO<P>::load(A.y + rhs * A.out_stride, A.g.ps, cb, yv);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < 24; ++k) {
+            const double d = (double)yv[k] - (double)acc[k];
+            s += d * d;
+            lo[k] = (float)d;
+        }
+        SpinorIO<P_F32>::store(A.out + rhs * A.out_stride, A.g.ps, cb, lo);
+        red[0] = s;
+        return;
     }
     if constexpr (RED == 4) {   // the residual y - (a x + b D in) is what is stored
         T yv[24];

@@ -58,10 +58,17 @@ static wd_status launch_k(wd_context ctx, const DslashArgs& A, const TuneParam& 
 }
 
 // The solvers' inner products (RED_NORM, RED_XDOT, RED_YDOT) are built without the dagger for
-// every precision; the float64 residuals (RED_RESID, RED_YDIFF) with and without it, in F64.
+// every precision, RED_NORM also with it in float32 and float64 (the accumulation precisions);
+// the CG residual update RED_CGR with the dagger for every precision; the float64 residuals
+// (RED_RESID, RED_YDIFF) with and without it and RED_RESLO without it, in F64.
 template <int P, int R>
 static wd_status launch_pr(wd_context ctx, const DslashArgs& A, const TuneParam& tp, int red, bool dag, unsigned nblk)
 {
+    if (red == RED_CGR) return dag ? launch_k<P, R, true, RED_CGR>(ctx, A, tp, nblk) : WD_EUNSUPPORTED;
+    if (red == RED_NORM && dag) {
+        if constexpr (P == P_F64 || P == P_F32) return launch_k<P, R, true, RED_NORM>(ctx, A, tp, nblk);
+        return WD_EUNSUPPORTED;
+    }
     if (red <= RED_YDOT) {
         if (dag) return WD_EUNSUPPORTED;
         switch (red) {
@@ -73,16 +80,20 @@ static wd_status launch_pr(wd_context ctx, const DslashArgs& A, const TuneParam&
     if constexpr (P == P_F64) {
         if (red == RED_RESID)
             return dag ? launch_k<P, R, true, RED_RESID>(ctx, A, tp, nblk) : launch_k<P, R, false, RED_RESID>(ctx, A, tp, nblk);
+        if (red == RED_RESLO) return dag ? WD_EUNSUPPORTED : launch_k<P, R, false, RED_RESLO>(ctx, A, tp, nblk);
         return dag ? launch_k<P, R, true, RED_YDIFF>(ctx, A, tp, nblk) : launch_k<P, R, false, RED_YDIFF>(ctx, A, tp, nblk);
     }
     return WD_EUNSUPPORTED;
 }
 
 wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, int red, const void* y,
-                            double* partials, int* nblocks)
+                            double* partials, int* nblocks, const double* coef)
 {
-    if (!c.x || c.nrhs != 1 || red < RED_NORM || red > RED_YDIFF || (red >= RED_YDOT && !y) || !partials || !nblocks) {
-        set_error("dslash: a fused reduction needs a x + b D in, one rhs (and y for RED_YDOT, RED_RESID, RED_YDIFF)");
+    const bool needs_y = red >= RED_YDOT && red <= RED_RESLO;
+    if (!c.x || c.nrhs != 1 || red < RED_NORM || red > RED_CGR || (needs_y && !y) || (red == RED_CGR && !coef) ||
+        !partials || !nblocks) {
+        set_error("dslash: a fused reduction needs a x + b D in, one rhs (and y for RED_YDOT, RED_RESID, RED_YDIFF, "
+                  "RED_RESLO; alpha in device memory for RED_CGR)");
         return WD_EINVAL;
     }
     // the launch shape tuned for the same launch without the reduction
@@ -97,6 +108,7 @@ wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, 
     }
     A.red = partials;
     A.y = (const char*)y;
+    A.coef = coef;
     *nblocks = (int)nblk;
     const bool r12 = c.recon == 12, dag = c.dagger != 0;
     wd_status st = WD_EINVAL;
@@ -108,8 +120,8 @@ wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, 
     default: set_error("dslash: bad precision %d", c.prec); return WD_EINVAL;
     }
     if (st == WD_EUNSUPPORTED)
-        set_error("dslash: fused reduction %d is built for %s only", red,
-                  red <= RED_YDOT ? "the launch without the dagger" : "float64");
+        set_error("dslash: fused reduction %d is not built for precision %d %s the dagger", red, c.prec,
+                  dag ? "with" : "without");
     return st;
 }
 

@@ -12,8 +12,8 @@
 // most `restart` iterations or until its residual estimate falls by
 // params->delta; x_e += e in float64 and rhat is recomputed, which decides
 // convergence.  At the end x_o = b_o + kappa D_oe x_e, which zeroes the odd rows
-// of b - M x and leaves rhat in the even rows; the full residual is recomputed
-// in float64 and reported.  Orthogonalisation is classical Gram-Schmidt applied
+// of b - M x and leaves rhat in the even rows; the even rows are recomputed in
+// float64 from the x_o that was built, and reported.  Orthogonalisation is classical Gram-Schmidt applied
 // twice: the first pass's coefficients never leave the device, the first pass's
 // update and the second pass's dots share one sweep over the basis, and each
 // iteration waits for the host once.  The plain solver is the fallback: a NaN,
@@ -80,14 +80,13 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     const size_t nh = 1;   // Krylov vectors: EVEN half fields
     const size_t v32 = half_bytes(G, WD_F32);
     const size_t h64 = half_bytes(G, WD_F64);
-    void *V, *Z, *wv, *e, *e64, *rhat, *r, *fa = nullptr, *fb = nullptr;
+    void *V, *Z, *wv, *e, *e64, *rhat, *fa = nullptr, *fb = nullptr;
     WD_TRY(ws_get(ctx, "fgmres.V", v32 * (m + 1), &V));
     WD_TRY(ws_get(ctx, "fgmres.Z", v32 * m, &Z));
     WD_TRY(ws_get(ctx, "fgmres.w", v32, &wv));
     WD_TRY(ws_get(ctx, "fgmres.e", v32, &e));
     WD_TRY(ws_get(ctx, "fgmres.e64", h64, &e64));
     WD_TRY(ws_get(ctx, "fgmres.rhat", h64, &rhat));
-    WD_TRY(ws_get(ctx, "fgmres.r", 2 * h64, &r));
     if (net) {
         int cmax = 0;
         for (int c : net->widths) cmax = c > cmax ? c : cmax;
@@ -98,7 +97,6 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     auto Vi = [&](int i) { return (void*)((char*)V + (size_t)i * v32); };
     auto Zi = [&](int i) { return (void*)((char*)Z + (size_t)i * v32); };
     char* x_e = (char*)x;
-    char* x_o = x_e + h64;
     const char* b_e = (const char*)b;
     const char* b_o = b_e + h64;
     void* bhat;
@@ -135,10 +133,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         return WD_OK;
     };
     auto finish_x = [&](double* rr) -> wd_status {   // x_o, then the full residual in float64
-        WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, (long long)h64, x_o, (long long)h64, b_o, (long long)h64, 1.0, kappa));
-        WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
-        WD_TRY(fetch_results(ctx, 1));
-        *rr = ctx->hres[0];
+        WD_TRY(eo_finish(g, kappa, b, x, rr));
         info->operator_applies++;
         return WD_OK;
     };

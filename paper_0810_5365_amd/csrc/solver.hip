@@ -67,31 +67,64 @@ struct CGProblem {
     wd_gauge g;
     double kappa;
     int subset;
-    const void* c;       // right-hand side of A x = c (float64)
-    const void* bhat;    // non-null: also track ||bhat - Mhat x|| (Wilson-system residual)
+    const void* c;       // right-hand side of A x = c (float64); null for the Wilson system
+    const void* bhat;    // the Wilson system on one parity: A x = Mhat^dag bhat, with the residual
+                         // ||bhat - Mhat x|| tracked as well
     double wnorm2;       // reference norm^2 for the Wilson-system residual
 };
 
-// r = c - A x in float64; ww = ||bhat - Mhat x||^2 when tracked.
-static wd_status true_residual(const CGProblem& P, const void* x, void* r, double* rr, double* ww)
+// General system: r = c - A x in float64 with rr = ||r||^2 (four float64 launches), then rs = r
+// at the accumulation precision.
+static wd_status residual_general(const CGProblem& P, int pacc, const void* x, void* r, void* rs, double* rr)
 {
     wd_context ctx = P.g->ctx;
     const Geom& G = P.g->geom;
     const size_t nh = halves_of(P.subset, 1);
-    const size_t bytes = half_bytes(G, WD_F64) * nh;
     void* t1;
-    WD_TRY(ws_get(ctx, "cg.t1", bytes, &t1));
-    // t1 = M x (with ||bhat - t1||^2 when tracked), then r = c - M^dag t1 with ||r||^2, each
-    // difference and norm taken by the launch that produces the operator's result
-    if (P.bhat) WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, WD_F64, x, t1, RED_YDIFF, P.bhat, 1));
-    else WD_TRY(op_M(P.g, P.kappa, P.subset, 0, WD_F64, 1, x, t1));
+    WD_TRY(ws_get(ctx, "cg.t1", half_bytes(G, WD_F64) * nh, &t1));
+    WD_TRY(op_M(P.g, P.kappa, P.subset, 0, WD_F64, 1, x, t1));
     WD_TRY(op_M_red(P.g, P.kappa, P.subset, 1, WD_F64, t1, r, RED_RESID, P.c, 0));
+    WD_TRY(fetch_results(ctx, 1));
+    *rr = ctx->hres[0];
+    return launch_convert(ctx, G, nh, WD_F64, r, pacc, rs);
+}
+
+// Wilson system: t = bhat - Mhat x in float64, kept at the accumulation precision, with ww =
+// ||t||^2 (two float64 launches), then rs = Mhat^dag t with rr = ||rs||^2 at that precision.
+// Mhat^dag (bhat - Mhat x) is the normal-equation residual c - A x: the cancellation happens in
+// the float64 difference, and the operator applied to that small vector only needs the
+// precision rs is kept in.  With x_zero the first step is a conversion of bhat.
+static wd_status residual_wilson(const CGProblem& P, int pacc, const void* x, bool x_zero, void* rs, double* rr,
+                                 double* ww)
+{
+    wd_context ctx = P.g->ctx;
+    const Geom& G = P.g->geom;
+    void* t;
+    WD_TRY(ws_get(ctx, "cg.t", half_bytes(G, pacc), &t));
+    if (x_zero) {
+        WD_TRY(launch_convert(ctx, G, 1, WD_F64, P.bhat, pacc, t));
+        WD_TRY(blas_norm2(ctx, G, 1, WD_F64, P.bhat, true));
+        *ww = ctx->hres[0];
+    } else {
+        WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, WD_F64, x, t, pacc == WD_F64 ? RED_RESID : RED_RESLO, P.bhat, 1));
+    }
+    WD_TRY(op_M_red(P.g, P.kappa, P.subset, 1, pacc, t, rs, RED_NORM, nullptr, 0));
     WD_TRY(fetch_results(ctx, 2));
     *rr = ctx->hres[0];
-    *ww = P.bhat ? ctx->hres[1] : -1.0;
+    if (!x_zero) *ww = ctx->hres[1];
     return WD_OK;
 }
 
+// One iteration keeps its scalars on the device (dres[CG_SLOT ..]):
+//   mp = M p, pap = ||M p||^2 = <p, A p>, alpha = rr / pap     (two launches and a sum)
+//   r -= alpha M^dag mp, rr_new = ||r||^2, beta = rr_new / rr  (two launches and a sum; A p is
+//                                                              never stored)
+//   xs += alpha p and p' = r + beta p                          (one sweep, into the other p buffer)
+// The sweep is queued before the host looks at pap and rr_new (which the sums write straight
+// into mapped host memory), so the host's wait overlaps it and the next iteration is queued
+// behind it.  When rr_new calls for a reliable update, xs
+// already holds alpha p: x += xs in float64, the residual is recomputed from x and p' is formed
+// again from the old p (still in its buffer) with beta = rr / rr_s.
 static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x, wd_solver_info* info)
 {
     wd_context ctx = P.g->ctx;
@@ -100,129 +133,146 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     const int pacc = pop == WD_F64 ? WD_F64 : WD_F32;
     const size_t nh = halves_of(P.subset, 1);
     const bool pure = prm.pure_sloppy != 0;
+    const bool wilson = P.bhat != nullptr;
     const double delta = resolve_delta(prm.delta, pop);
     const bool use_delta = pop != WD_F64 && delta > 0.0;
 
-    void *r, *rs, *xs, *p, *ap, *mp;
-    WD_TRY(ws_get(ctx, "cg.r", half_bytes(G, WD_F64) * nh, &r));
+    void *r = nullptr, *rs, *xs, *pa, *pb, *mp;
+    if (!wilson) WD_TRY(ws_get(ctx, "cg.r", half_bytes(G, WD_F64) * nh, &r));
     WD_TRY(ws_get(ctx, "cg.rs", half_bytes(G, pacc) * nh, &rs));
     WD_TRY(ws_get(ctx, "cg.xs", half_bytes(G, pacc) * nh, &xs));
-    WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &p));
-    // on one parity A p = Mhat^dag (Mhat p) is formed in place of Mhat p (the fused update of
-    // Mhat^dag reads x at the site it writes), so the iteration touches one field fewer and
-    // more of its fields stay in the last-level cache; on the full lattice it cannot be
-    if (P.subset == WD_FULL) WD_TRY(ws_get(ctx, "cg.ap", half_bytes(G, pop) * nh, &ap));
+    WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &pa));
+    WD_TRY(ws_get(ctx, "cg.p2", half_bytes(G, pop) * nh, &pb));
     WD_TRY(ws_get(ctx, "cg.mp", half_bytes(G, pop) * nh, &mp));
-    if (P.subset != WD_FULL) ap = mp;
+    *info = wd_solver_info{};
+    std::vector<double> alphas, betas;   // for the Ritz-value estimates
 
-    WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
-    const double cc = ctx->hres[0];
+    // cc = ||c||^2; for the Wilson system c = Mhat^dag bhat is formed at the accumulation
+    // precision (into rs: with a zero guess it is the first residual)
+    const bool x_zero = is_zero_f64(ctx, G, nh, x);
+    double cc, rr = 0.0, ww = -1.0;
+    if (wilson) {
+        WD_TRY(residual_wilson(P, pacc, nullptr, true, rs, &cc, &ww));
+        if (!std::isfinite(ww)) cc = ww;
+    } else {
+        WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
+        cc = ctx->hres[0];
+    }
     const double tol2 = prm.tol * prm.tol;
     const double target_r = tol2 * cc;
     const double target_w = tol2 * P.wnorm2;
-    *info = wd_solver_info{};
-    std::vector<double> alphas, betas;   // for the Ritz-value estimates
     if (!std::isfinite(cc)) {   // NaN or Inf in the source: x is left as it was
         set_error("CG: the right-hand side holds NaN or Inf");
         info->true_resid = cc;
-        info->true_resid_M = P.bhat ? cc : -1.0;
+        info->true_resid_M = wilson ? cc : -1.0;
         info->status = WD_ENAN;
         return WD_ENAN;
     }
     if (!(cc > 0.0)) {
         WD_TRY(blas_zero(ctx, G, nh, WD_F64, x));
         info->true_resid = 0.0;
-        info->true_resid_M = P.bhat ? 0.0 : -1.0;
+        info->true_resid_M = wilson ? 0.0 : -1.0;
         info->status = WD_OK;
         return WD_OK;
     }
 
-    double rr, ww;
-    if (is_zero_f64(ctx, G, nh, x)) {   // zero guess: r = c and bhat - Mhat x = bhat, without the operator
-        WD_TRY(launch_convert(ctx, G, nh, WD_F64, P.c, WD_F64, r));
+    // residual of the current x into rs (with rr, and ww for the Wilson system)
+    auto residual = [&]() -> wd_status {
+        if (wilson) return residual_wilson(P, pacc, x, false, rs, &rr, &ww);
+        return residual_general(P, pacc, x, r, rs, &rr);
+    };
+    if (x_zero) {   // the residual is c itself, already at hand
         rr = cc;
-        ww = -1.0;
-        if (P.bhat) {
-            WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.bhat, true));
-            ww = ctx->hres[0];
-        }
+        if (!wilson) WD_TRY(launch_convert(ctx, G, nh, WD_F64, P.c, pacc, rs));
     } else {
-        WD_TRY(true_residual(P, x, r, &rr, &ww));
+        WD_TRY(residual());
         info->operator_applies++;
     }
-    auto converged = [&]() { return P.bhat ? ww <= target_w : rr <= target_r; };
+    auto converged = [&]() { return wilson ? ww <= target_w : rr <= target_r; };
     wd_status status = WD_ENOCONV;
     if (converged()) status = WD_OK;
 
     // sloppy residual level that triggers a float64 check of convergence
-    double trigger = P.bhat ? (ww > 0 ? rr / ww : 1.0) * target_w : target_r;
-    bool xs_dirty = false;
+    double trigger = wilson ? (ww > 0 ? rr / ww : 1.0) * target_w : target_r;
+    bool xs_live = false;   // xs holds a part of the solution not yet in x
+    bool stale = false;     // x (with xs) has changed since rr, ww were computed
     if (status != WD_OK) {
-        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pacc, rs));
-        WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pop, p));
-        WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
+        void* p = pa;    // the search direction of this iteration
+        void* pn = pb;   // the next one
+        WD_TRY(launch_convert(ctx, G, nh, pacc, rs, pop, p));
+        WD_TRY(blas_cg_set(ctx, rr, 0.0));
         double rr_s = rr, maxrr = rr;
+        const double* dalpha = ctx->dres + CG_SLOT + CG_ALPHA;   // read by the launch that updates r
         while (info->iters < prm.maxiter) {
-            // A p = M^dag (M p), and <p, A p> = ||M p||^2 summed by the kernel that writes M p
-            WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, pop, p, mp, RED_NORM, nullptr, 0));
-            WD_TRY(op_M(P.g, P.kappa, P.subset, 1, pop, 1, mp, ap));
-            WD_TRY(fetch_results(ctx, 1));
+            int n = 0;
+            blas_cg_arm(ctx);
+            WD_TRY(op_M_red_partials(P.g, P.kappa, P.subset, 0, pop, p, mp, RED_NORM, nullptr, nullptr, &n));
+            WD_TRY(blas_cg_coef(ctx, n, 0));
+            WD_TRY(op_M_red_partials(P.g, P.kappa, P.subset, 1, pop, mp, rs, RED_CGR, nullptr, dalpha, &n));
+            WD_TRY(blas_cg_coef(ctx, n, 1));
+            WD_TRY(blas_cg_xp(ctx, G, nh, pacc, xs, xs_live ? 0 : 1, rs, pop, p, pn));
+            WD_TRY(blas_cg_wait(ctx));
             info->operator_applies++;
-            const double pap = ctx->hres[0];
-            if (!std::isfinite(pap) || !(pap > 0.0)) {
+            const double pap = ctx->hres[CG_SLOT + CG_PAP];
+            if (!std::isfinite(pap) || !(pap > 0.0)) {   // rs and xs are spoilt; x holds the last update
                 set_error("CG breakdown: <p, A p> = %g at iteration %d", pap, info->iters);
                 status = WD_ENAN;
+                xs_live = false;
                 break;
             }
-            const double alpha = rr_s / pap;
-            alphas.push_back(alpha);
-            WD_TRY(blas_cg_xr(ctx, G, nh, pacc, xs, rs, pop, p, ap, alpha, true));
-            xs_dirty = true;
-            double rr_new = ctx->hres[0];
+            alphas.push_back(rr_s / pap);
+            double rr_new = ctx->hres[CG_SLOT + CG_RRNEW];
             info->iters++;
+            xs_live = true;
+            stale = true;
             if (!std::isfinite(rr_new)) {
                 set_error("CG: non-finite residual at iteration %d", info->iters);
                 status = WD_ENAN;
+                xs_live = false;
                 break;
             }
-            if (pure) {
-                if (rr_new <= trigger) break;
-            } else if ((use_delta && rr_new < delta * delta * maxrr) || rr_new <= trigger) {
-                // reliable update: fold the sloppy solution into x and recompute r in float64
+            const bool done_sloppy = pure && rr_new <= trigger;
+            const bool reliable = !pure && ((use_delta && rr_new < delta * delta * maxrr) || rr_new <= trigger);
+            if (done_sloppy || reliable) {
                 WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
-                WD_TRY(blas_zero(ctx, G, nh, pacc, xs));
-                xs_dirty = false;
-                WD_TRY(true_residual(P, x, r, &rr, &ww));
+                xs_live = false;
+                if (done_sloppy) break;
+                // reliable update: the residual recomputed from x, the recurrence restarted from it
+                WD_TRY(residual());
+                stale = false;
                 info->operator_applies++;
                 info->reliable_updates++;
                 if (converged()) {
                     status = WD_OK;
                     break;
                 }
-                if (P.bhat && ww > 0) trigger = rr / ww * target_w;
-                WD_TRY(launch_convert(ctx, G, nh, WD_F64, r, pacc, rs));
+                if (wilson && ww > 0) trigger = rr / ww * target_w;
                 rr_new = rr;
                 maxrr = rr;
+                const double beta = rr_new / rr_s;
+                betas.push_back(beta);
+                WD_TRY(blas_cg_set(ctx, rr_new, beta));
+                WD_TRY(blas_cg_xp(ctx, G, nh, pacc, xs, 2, rs, pop, p, pn));
+            } else {
+                if (rr_new > maxrr) maxrr = rr_new;
+                betas.push_back(rr_new / rr_s);
             }
-            if (rr_new > maxrr) maxrr = rr_new;
-            const double beta = rr_new / rr_s;
-            betas.push_back(beta);
-            WD_TRY(blas_cg_p(ctx, G, nh, pacc, rs, pop, p, beta));
+            std::swap(p, pn);
             rr_s = rr_new;
         }
     }
-    if (xs_dirty) {   // else rr, ww are those of the last reliable update, already of this x
-        WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
-        WD_TRY(true_residual(P, x, r, &rr, &ww));
+    if (xs_live) WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+    if (stale) {   // else rr, ww are those of the last reliable update, already of this x
+        WD_TRY(residual());
         info->operator_applies++;
     }
     info->true_resid = std::sqrt(rr / cc);
-    info->true_resid_M = P.bhat ? std::sqrt(ww / P.wnorm2) : -1.0;
+    info->true_resid_M = wilson ? std::sqrt(ww / P.wnorm2) : -1.0;
     if (status != WD_ENAN) cg_ritz_extremes(alphas, betas, &info->lambda_min, &info->lambda_max);
     if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
     if (status == WD_ENOCONV)
         set_error("CG did not reach tol %g in %d iterations (residual %g)", prm.tol, info->iters,
-                  P.bhat ? info->true_resid_M : info->true_resid);
+                  wilson ? info->true_resid_M : info->true_resid);
     info->status = status;
     return status;
 }
@@ -291,25 +341,19 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     const char* b_e = (const char*)b;
     const char* b_o = b_e + hb;
     char* x_e = (char*)x;
-    char* x_o = x_e + hb;
-    void *bhat, *c;
+    void* bhat;
     WD_TRY(ws_get(ctx, "wilson.bhat", hb, &bhat));
-    WD_TRY(ws_get(ctx, "wilson.c", hb, &c));
-    // bhat = b_e + kappa D_eo b_o ; c = Mhat^dagger bhat
+    // bhat = b_e + kappa D_eo b_o; CG solves Mhat^dagger Mhat x_e = Mhat^dagger bhat
     WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, hb, bhat, hb, b_e, hb, 1.0, kappa));
-    WD_TRY(op_M(g, kappa, WD_EVEN, 1, WD_F64, 1, bhat, c));
     WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
     const double bb = ctx->hres[0];
-    CGProblem P{g, kappa, WD_EVEN, c, bhat, bb};
+    CGProblem P{g, kappa, WD_EVEN, nullptr, bhat, bb};
     wd_status s = cg_run(P, *params, x_e, info);
     if (s != WD_OK && s != WD_ENOCONV) return s;
-    // x_o = b_o + kappa D_oe x_e ; then the full-system residual in float64
-    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_o, hb, b_o, hb, 1.0, kappa));
-    void* r;
-    WD_TRY(ws_get(ctx, "wilson.r", 2 * hb, &r));
-    WD_TRY(op_M_red(g, kappa, WD_FULL, 0, WD_F64, x, r, RED_RESID, b, 0));   // r = b - M x, ||r||^2
-    WD_TRY(fetch_results(ctx, 1));
-    info->true_resid_M = bb > 0 ? std::sqrt(ctx->hres[0] / bb) : 0.0;
+    // x_o, then the full-system residual in float64
+    double rr;
+    WD_TRY(eo_finish(g, kappa, b, x, &rr));
+    info->true_resid_M = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     info->operator_applies++;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;

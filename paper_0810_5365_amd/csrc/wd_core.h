@@ -125,14 +125,19 @@ std::string dslash_key(const Geom& g, const DslashCall& c);
 // ---- dslash_red.hip: a fused-update launch (c.x set, one rhs) that also sums a reduction of
 // its result per workgroup: RED_NORM |out|^2 (1 value); RED_XDOT <out, x> and |out|^2,
 // RED_YDOT <y, out> and |out|^2 (3 values; y a half field at c.prec); these without the
-// dagger.  In float64, with or without the dagger: RED_RESID stores out = y - (a x + b D in)
-// and sums |out|^2; RED_YDIFF sums |y - out|^2 (1 value each).  Value v of workgroup k lands
-// in partials[v * nblocks + k]; the caller sizes partials for 3 values per workgroup of 64
-// sites.
-enum { RED_NORM = 1, RED_XDOT = 2, RED_YDOT = 3, RED_RESID = 4, RED_YDIFF = 5 };
+// dagger; RED_NORM also with the dagger in float32 and float64.  In float64, with or without
+// the dagger: RED_RESID stores out = y - (a x + b D in) and sums |out|^2; RED_YDIFF sums
+// |y - out|^2.  RED_RESLO (float64, no dagger) is RED_RESID with out stored in float32 and the
+// sum taken before that rounding.  RED_CGR (every precision, with the dagger; the CG residual
+// update) does not store a x + b D in: it updates r -= alpha (a x + b D in) in place, r = c.out
+// held at the accumulation precision (float64 for a float64 launch, else float32), alpha =
+// coef[0] read from device memory, and sums |r|^2 of the stored r.  Value v of workgroup k
+// lands in partials[v * nblocks + k]; the caller sizes partials for 3 values per workgroup of
+// 64 sites.
+enum { RED_NORM = 1, RED_XDOT = 2, RED_YDOT = 3, RED_RESID = 4, RED_YDIFF = 5, RED_RESLO = 6, RED_CGR = 7 };
 constexpr int red_values(int red) { return red == RED_XDOT || red == RED_YDOT ? 3 : 1; }
 wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, int red, const void* y,
-                            double* partials, int* nblocks);
+                            double* partials, int* nblocks, const double* coef = nullptr);
 // ---- dslash_mrhs.hip: 16 rhs per wave with the colour multiply on the matrix cores ----
 bool mrhs_eligible(const DslashCall& c);
 wd_status launch_dslash_mrhs(wd_context ctx, const Geom& g, const DslashCall& c);
@@ -152,11 +157,23 @@ wd_status blas_caxpy(wd_context ctx, const Geom& g, size_t nhalves, int prec, do
 wd_status blas_zero(wd_context ctx, const Geom& g, size_t nhalves, int prec, void* x);
 // y = a*x + b*y with real a, b (y, x may differ in precision: x at px, y at py)
 wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nhalves, int px, const void* x, double a, int py, void* y, double b);
-// CG step: x += alpha p; r -= alpha Ap; ||r||^2 -> dres[0]  (x, r at pacc; p, Ap at pop)
-wd_status blas_cg_xr(wd_context ctx, const Geom& g, size_t nhalves, int pacc, void* x, void* r, int pop, const void* p,
-                     const void* ap, double alpha, bool fetch);
-// CG step: p = r + beta p (r at pacc, p at pop)
-wd_status blas_cg_p(wd_context ctx, const Geom& g, size_t nhalves, int pacc, const void* r, int pop, void* p, double beta);
+// CG with its scalars on the device, in dres[CG_SLOT + i] (and the sums in hres[CG_SLOT + i]):
+// CG_RR the current sloppy ||r||^2, CG_PAP <p, A p>, CG_ALPHA = rr / pap, CG_RRNEW, CG_BETA.
+constexpr int CG_SLOT = 248, CG_RR = 0, CG_PAP = 1, CG_ALPHA = 2, CG_RRNEW = 3, CG_BETA = 4, CG_NSLOTS = 5;
+// finish the one-value partials in ctx->partials[0 .. nblk): mode 0 sets pap and alpha, mode 1
+// sets rr_new, beta = rr_new / rr and then rr = rr_new
+wd_status blas_cg_coef(wd_context ctx, int nblk, int mode);
+// rr and beta from the host (after a reliable update)
+wd_status blas_cg_set(wd_context ctx, double rr, double beta);
+// Before an iteration: mark hres[CG_SLOT + CG_PAP] and [CG_SLOT + CG_RRNEW] as pending.  After
+// queueing it: wait until the coefficient kernels have written both (spinning on the mapped
+// host buffer; with no mapped buffer, a stream synchronisation)
+void blas_cg_arm(wd_context ctx);
+wd_status blas_cg_wait(wd_context ctx);
+// x += alpha p (xmode 0), x = alpha p (1) or x untouched (2); then q = r + beta p (q may be p).
+// x, r at pacc; p, q at pop
+wd_status blas_cg_xp(wd_context ctx, const Geom& g, size_t nhalves, int pacc, void* x, int xmode, const void* r,
+                     int pop, const void* p, void* q);
 wd_status fetch_results(wd_context ctx, int n);
 // true when the float64 field (nhalves half fields) is all zeros (a norm sweep; false on error)
 bool is_zero_f64(wd_context ctx, const Geom& g, size_t nhalves, const void* x);

@@ -257,6 +257,26 @@ def test_cg_even_odd_normal_equations(w, ctx, sloppy):
     assert abs(res - info.true_resid) <= 1e-3 * tol + 1e-2 * res
 
 
+@pytest.mark.parametrize("sloppy", ["f64", "f32", "bf16"])
+def test_cg_full_lattice_normal_equations(w, ctx, sloppy):
+    """CG on M^dag M x = c over both parities (the residual update fused into both launches
+    of M^dag), checked by the oracle's float64 residual."""
+    dims, kappa, tol = (8, 8, 8, 8), 0.12, 1e-10
+    U, g = gauge(w, ctx, dims, 0.6, 3005, 12)
+    lat = w.lattice(dims, BC)
+    c = source(w, dims, w.FULL, 37)
+    fb = w.pack(ctx, lat, w.FULL, w.F64, c)
+    fx = w.pack(ctx, lat, w.FULL, w.F64, np.zeros_like(c))
+    prm = w.solver_params(tol=tol, maxiter=3000, sloppy=w.PREC_BY_NAME[sloppy])
+    info = w.WdSolverInfo()
+    w.wd_cg_solve(g.handle, kappa, w.FULL, ctypes.byref(prm), fb.data_ptr(), fx.data_ptr(), ctypes.byref(info))
+    x = w.unpack(ctx, lat, w.FULL, w.F64, fx, c.shape)
+    res = orc.rel_residual(lambda v: orc.apply_mdagm(U, v, kappa, BC), x, c)
+    assert info.status == w.WD_OK
+    assert res <= 1.05 * tol, (res, info.as_dict())
+    assert abs(res - info.true_resid) <= 1e-3 * tol + 1e-2 * res
+
+
 @pytest.mark.parametrize("sloppy", ["f32", "bf16"])
 def test_wilson_solve_full_system(w, ctx, sloppy):
     dims, kappa, tol = (8, 8, 8, 16), 0.1245, 1e-10
