@@ -187,6 +187,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
         set_error("wd_bicgstab_solve: the source holds NaN or Inf");
         info->true_resid = info->true_resid_M = bb;
         info->status = WD_ENAN;
+        hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         return WD_ENAN;
     }
@@ -201,6 +202,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     info->true_resid_M = bb > 0 ? std::sqrt(rr_full / bb) : 0.0;
     info->operator_applies++;
     info->status = s;
+    hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;
 }

@@ -82,17 +82,59 @@ static int red_blocks(long long nsites)
     return (int)(b < RED_MAXBLOCKS ? (b < 1 ? 1 : b) : RED_MAXBLOCKS);
 }
 
+// With a mapped host buffer the host waits for results by spinning on the slots themselves:
+// each is armed with a NaN payload before the kernel that writes it is queued (no arithmetic
+// produces that payload).  A stream or event wait would also write the whole L2 back to memory
+// and leave the GPU idle for tens of microseconds per wait.
+constexpr uint64_t RES_PENDING = 0x7ff4c0ffee000001ull;
+
+static void arm_slots(wd_context ctx, int slot, int n)
+{
+    if (!ctx->hres_dev) return;
+    volatile uint64_t* h = (volatile uint64_t*)ctx->hres;
+    for (int i = 0; i < n; ++i) h[slot + i] = RES_PENDING;
+}
+
+static wd_status wait_slots(wd_context ctx, int slot, int n)
+{
+    volatile uint64_t* h = (volatile uint64_t*)ctx->hres;
+    auto ready = [&]() {
+        for (int i = 0; i < n; ++i)
+            if (h[slot + i] == RES_PENDING) return false;
+        return true;
+    };
+    auto last = std::chrono::steady_clock::now();
+    for (unsigned spins = 1; !ready(); ++spins) {
+        // every 2 ms (a query takes the runtime's locks, so not more often): once the stream has
+        // drained, the slots hold whatever was written, and a HIP error ends the wait
+        if ((spins & 255u) == 0 && std::chrono::steady_clock::now() - last > std::chrono::milliseconds(2)) {
+            last = std::chrono::steady_clock::now();
+            const hipError_t e = hipStreamQuery(ctx->stream);
+            if (e == hipSuccess) break;
+            if (e != hipErrorNotReady) {
+                set_error("HIP error while waiting for reduction results: %s", hipGetErrorString(e));
+                return WD_EHIP;
+            }
+        }
+        __builtin_ia32_pause();
+    }
+    std::atomic_thread_fence(std::memory_order_acquire);
+    return WD_OK;
+}
+
 // Values land in dres[slot ..] and its host copy hres[slot ..] (mapped: written by the
 // kernel; else copied behind it on the stream).
 static wd_status finish(wd_context ctx, int nblk, int n, bool fetch, int slot = 0)
 {
+    arm_slots(ctx, slot, n);
     hipLaunchKernelGGL(finish_kernel, dim3(n), dim3(RED_BLOCK), 0, ctx->stream, ctx->partials, nblk, ctx->dres + slot,
                        ctx->hres_dev ? ctx->hres_dev + slot : nullptr);
     WD_LAUNCHED();
     if (!ctx->hres_dev && slot != 0)
         WD_HIP(hipMemcpyAsync(ctx->hres + slot, ctx->dres + slot, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
-    if (fetch) return fetch_results(ctx, slot == 0 ? n : 0);
-    return WD_OK;
+    if (!fetch) return WD_OK;
+    if (ctx->hres_dev) return wait_slots(ctx, slot, n);
+    return fetch_results(ctx, slot == 0 ? n : 0);
 }
 
 bool is_zero_f64(wd_context ctx, const Geom& g, size_t nhalves, const void* x)
@@ -104,8 +146,9 @@ wd_status reduce_partials(wd_context ctx, int nblk, int n, int slot) { return fi
 
 wd_status fetch_results(wd_context ctx, int n)
 {
-    if (!ctx->hres_dev)   // no mapped host buffer: copy the results over
-        WD_HIP(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
+    if (ctx->hres_dev) return wait_slots(ctx, 0, n);
+    // no mapped host buffer: copy the results over
+    WD_HIP(hipMemcpyAsync(ctx->hres, ctx->dres, sizeof(double) * n, hipMemcpyDeviceToHost, ctx->stream));
     WD_HIP(hipStreamSynchronize(ctx->stream));
     return WD_OK;
 }
@@ -338,19 +381,7 @@ wd_status blas_cg_coef(wd_context ctx, int nblk, int mode)
     return WD_OK;
 }
 
-// The host arms the two slots it waits for with a NaN payload that no arithmetic produces; the
-// coefficient kernels overwrite them in the mapped host buffer, and the host spins on them
-// instead of synchronising the stream (a stream or event wait would also write the whole L2
-// back to memory, several microseconds per iteration).
-constexpr uint64_t CG_PENDING = 0x7ff4c0ffee000001ull;
-
-void blas_cg_arm(wd_context ctx)
-{
-    if (!ctx->hres_dev) return;
-    volatile uint64_t* h = (volatile uint64_t*)(ctx->hres + CG_SLOT);
-    h[CG_PAP] = CG_PENDING;
-    h[CG_RRNEW] = CG_PENDING;
-}
+void blas_cg_arm(wd_context ctx) { arm_slots(ctx, CG_SLOT + CG_PAP, 2); }
 
 wd_status blas_cg_wait(wd_context ctx)
 {
@@ -358,29 +389,7 @@ wd_status blas_cg_wait(wd_context ctx)
         WD_HIP(hipStreamSynchronize(ctx->stream));
         return WD_OK;
     }
-    volatile uint64_t* h = (volatile uint64_t*)(ctx->hres + CG_SLOT);
-    auto last = std::chrono::steady_clock::now();
-    for (unsigned spins = 1;; ++spins) {
-        if (h[CG_PAP] != CG_PENDING && h[CG_RRNEW] != CG_PENDING) break;
-        // every 2 ms (a query takes the runtime's locks, so not more often): a stream that has
-        // drained without writing them is an error
-        if ((spins & 255u) == 0 && std::chrono::steady_clock::now() - last > std::chrono::milliseconds(2)) {
-            last = std::chrono::steady_clock::now();
-            const hipError_t e = hipStreamQuery(ctx->stream);
-            if (e == hipSuccess) {
-                if (h[CG_PAP] != CG_PENDING && h[CG_RRNEW] != CG_PENDING) break;
-                set_error("CG: the stream finished without writing its coefficients");
-                return WD_EHIP;
-            }
-            if (e != hipErrorNotReady) {
-                set_error("HIP error while waiting for the CG coefficients: %s", hipGetErrorString(e));
-                return WD_EHIP;
-            }
-        }
-        __builtin_ia32_pause();
-    }
-    std::atomic_thread_fence(std::memory_order_acquire);
-    return WD_OK;
+    return wait_slots(ctx, CG_SLOT + CG_PAP, 2);
 }
 
 wd_status blas_cg_set(wd_context ctx, double rr, double beta)

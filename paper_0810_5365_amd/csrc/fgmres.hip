@@ -365,6 +365,7 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
         info->fell_back = 1;
     }
     info->status = s;
+    hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;
 }

@@ -317,6 +317,7 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
     const auto t0 = std::chrono::steady_clock::now();
     CGProblem P{g, kappa, (int)subset, b, nullptr, 0.0};
     wd_status s = cg_run(P, *params, x, info);
+    hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;
 }
@@ -355,6 +356,7 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     WD_TRY(eo_finish(g, kappa, b, x, &rr));
     info->true_resid_M = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     info->operator_applies++;
+    hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;
 }

@@ -158,8 +158,9 @@ wd_status blas_zero(wd_context ctx, const Geom& g, size_t nhalves, int prec, voi
 // y = a*x + b*y with real a, b (y, x may differ in precision: x at px, y at py)
 wd_status blas_axpby(wd_context ctx, const Geom& g, size_t nhalves, int px, const void* x, double a, int py, void* y, double b);
 // CG with its scalars on the device, in dres[CG_SLOT + i] (and the sums in hres[CG_SLOT + i]):
-// CG_RR the current sloppy ||r||^2, CG_PAP <p, A p>, CG_ALPHA = rr / pap, CG_RRNEW, CG_BETA.
-constexpr int CG_SLOT = 248, CG_RR = 0, CG_PAP = 1, CG_ALPHA = 2, CG_RRNEW = 3, CG_BETA = 4, CG_NSLOTS = 5;
+// CG_RR the current sloppy ||r||^2, CG_ALPHA = rr / pap, CG_BETA, and the two the host reads,
+// CG_PAP <p, A p> and CG_RRNEW (adjacent).
+constexpr int CG_SLOT = 248, CG_RR = 0, CG_ALPHA = 1, CG_BETA = 2, CG_PAP = 3, CG_RRNEW = 4, CG_NSLOTS = 5;
 // finish the one-value partials in ctx->partials[0 .. nblk): mode 0 sets pap and alpha, mode 1
 // sets rr_new, beta = rr_new / rr and then rr = rr_new
 wd_status blas_cg_coef(wd_context ctx, int nblk, int mode);
