@@ -415,10 +415,13 @@ __device__ __forceinline__ void wave_lds_sync()
 // One path in two halves so that the loads of path p + 1 are in flight while path p is
 // transported, staged and multiplied (the layer is latency-bound on small lattices:
 // one wave per 64 sites walks all nine paths).
-template <int R, int CIN> struct MfRaw {
-    float4 l[R == 12 ? 3 : 4];   // link planes as loaded (row 2 rebuilt later for 12 reals)
-    float2 l18;                  // last two reals of an 18-real link
-    float2 v[CIN][3];            // neighbour features, channel b, colour k
+// L16: the links are read as float16 codes (12 reals: 8 + 4 codes, 24 B instead of 48 B).
+template <int R, int CIN, bool L16 = false> struct MfRaw {
+    float4 l[L16 ? 1 : (R == 12 ? 3 : 4)];   // link planes as loaded (row 2 rebuilt later for 12 reals)
+    float2 l18;                              // last two reals of an 18-real link
+    uint4 h8;                                // L16: codes of reals 0..7
+    uint2 h4;                                // L16: codes of reals 8..11
+    float2 v[CIN][3];                        // neighbour features, channel b, colour k
 };
 
 // bf16 feature pair (re in the low half, as cvt_bf16x2 packs it) -> float2
@@ -429,9 +432,9 @@ __device__ __forceinline__ float2 bf16x2_to_f2(uint32_t h)
 
 // HF: the feature tensors (input and output, where not a spinor) hold bf16 pairs, one
 // uint32 per complex at the float2 layout's index
-template <int PATH, int R, int CIN, bool SIN, bool HF>
+template <int PATH, int R, int CIN, bool SIN, bool HF, bool L16>
 __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
-                                        MfRaw<R, CIN>& x)
+                                        MfRaw<R, CIN, L16>& x)
 {
     const int Vh = A.g.Vh;
     uint32_t src = cb;
@@ -441,11 +444,19 @@ __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int p
         constexpr bool FWD = PATH <= 4;
         const uint32_t nb = neighbour<MU, FWD>(A.g, cb, c);
         const int lpar = FWD ? par : 1 - par;
-        const float4* grp =
-            (const float4*)(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps) + (FWD ? cb : nb);
+        const uint32_t ls = FWD ? cb : nb;
+        if constexpr (L16) {   // the 16-bit 12-real layout: a plane of uint4, then a plane of uint2
+            static_assert(R == 12, "16-bit links are read in the 12-real layout only");
+            const uint4* grp = (const uint4*)(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F16, 12) * A.g.ps);
+            x.h8 = grp[ls];
+            x.h4 = ((const uint2*)(grp + (size_t)A.g.ps))[ls];
+        } else {
+            const float4* grp =
+                (const float4*)(A.gauge + (size_t)(2 * MU + lpar) * link_site_bytes(P_F32, R) * A.g.ps) + ls;
 #pragma unroll
-        for (int k = 0; k < (R == 12 ? 3 : 4); ++k) x.l[k] = grp[(size_t)k * A.g.ps];
-        if constexpr (R == 18) x.l18 = ((const float2*)(grp - (FWD ? cb : nb) + (size_t)4 * A.g.ps))[FWD ? cb : nb];
+            for (int k = 0; k < (R == 12 ? 3 : 4); ++k) x.l[k] = grp[(size_t)k * A.g.ps];
+            if constexpr (R == 18) x.l18 = ((const float2*)(grp - ls + (size_t)4 * A.g.ps))[ls];
+        }
         src = nb;
         spar = 1 - par;
     }
@@ -473,17 +484,26 @@ __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int p
         for (int k = 0; k < 3; ++k) x.v[b][k] = site[(size_t)(b * 6 + k) * Vh];
 }
 
-template <int PATH, int R, int CIN>
+template <int PATH, int R, int CIN, bool L16>
 __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int lane, uint16_t* B,
-                                           const MfRaw<R, CIN>& x, const bf16x4& Af, f32x4* acc)
+                                           const MfRaw<R, CIN, L16>& x, const bf16x4& Af, f32x4* acc)
 {
     float u[18];
     if constexpr (PATH > 0) {
         constexpr int MU = (PATH - 1) & 3;
         constexpr bool FWD = PATH <= 4;
+        if constexpr (L16) {
+            const uint32_t h[6] = {x.h8.x, x.h8.y, x.h8.z, x.h8.w, x.h4.x, x.h4.y};
 #pragma unroll
-        for (int k = 0; k < (R == 12 ? 3 : 4); ++k) {
-            u[4 * k] = x.l[k].x; u[4 * k + 1] = x.l[k].y; u[4 * k + 2] = x.l[k].z; u[4 * k + 3] = x.l[k].w;
+            for (int k = 0; k < 6; ++k) {
+                u[2 * k] = h2f<P_F16>(h[k]);
+                u[2 * k + 1] = h2f<P_F16>(h[k] >> 16);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < (R == 12 ? 3 : 4); ++k) {
+                u[4 * k] = x.l[k].x; u[4 * k + 1] = x.l[k].y; u[4 * k + 2] = x.l[k].z; u[4 * k + 3] = x.l[k].w;
+            }
         }
         if constexpr (R == 18) {
             u[16] = x.l18.x;
@@ -525,14 +545,14 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
 }
 
 // paths P..LAST, each one's loads issued before the previous one's arithmetic
-template <int P, int LAST, int R, int CIN, bool SIN, bool HF>
+template <int P, int LAST, int R, int CIN, bool SIN, bool HF, bool L16>
 __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
-                                        int lane, uint16_t* B, const bf16x4* Af, f32x4* acc, MfRaw<R, CIN>& cur,
-                                        MfRaw<R, CIN>& nxt)
+                                        int lane, uint16_t* B, const bf16x4* Af, f32x4* acc, MfRaw<R, CIN, L16>& cur,
+                                        MfRaw<R, CIN, L16>& nxt)
 {
-    if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN, HF>(A, in, par, cb, c, nxt);
-    mf_compute<P, R, CIN>(A, c, lane, B, cur, Af[P], acc);
-    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
+    if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN, HF, L16>(A, in, par, cb, c, nxt);
+    mf_compute<P, R, CIN, L16>(A, c, lane, B, cur, Af[P], acc);
+    if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
 }
 
 // SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out);
@@ -541,7 +561,8 @@ __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int p
 // taking the stay path and the forward hops, the second the backward hops; the second's
 // accumulators are added to the first's through LDS.  With few sites (one wave per SIMD
 // otherwise) this halves each wave's chain of dependent path loads.
-template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF, bool SPLIT>
+// L16: links read as float16 codes (A.gauge holds the 16-bit 12-real layout).
+template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF, bool SPLIT, bool L16 = false>
 __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
@@ -597,15 +618,15 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     // sources are all known zeros is skipped (par is wave-uniform).
     const bool skip_stay = A.zero_par >= 0 && par == A.zero_par;
     const bool skip_hops = A.zero_par >= 0 && 1 - par == A.zero_par;
-    MfRaw<R, CIN> ra, rb;
+    MfRaw<R, CIN, L16> ra, rb;
     if constexpr (SPLIT) {
         f32x4* rs = red[wave >> 1];
         if ((wave & 1) == 0) {
-            mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
-            mf_pipe<0, 4, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+            mf_load<0, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
+            mf_pipe<0, 4, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
         } else {
-            mf_load<5, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
-            mf_pipe<5, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+            mf_load<5, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
+            mf_pipe<5, 8, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
 #pragma unroll
             for (int t = 0; t < 12; ++t) rs[t * 64 + lane] = acc[t];
         }
@@ -614,14 +635,14 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
 #pragma unroll
         for (int t = 0; t < 12; ++t) acc[t] += rs[t * 64 + lane];
     } else if (skip_hops) {
-        mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
-        mf_compute<0, R, CIN>(A, c, lane, B, ra, Af[0], acc);
+        mf_load<0, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
+        mf_compute<0, R, CIN, L16>(A, c, lane, B, ra, Af[0], acc);
     } else if (skip_stay) {
-        mf_load<1, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
-        mf_pipe<1, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<1, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
+        mf_pipe<1, 8, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     } else {
-        mf_load<0, R, CIN, SIN, HF>(A, in, par, cb, c, ra);
-        mf_pipe<0, 8, R, CIN, SIN, HF>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
+        mf_load<0, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
+        mf_pipe<0, 8, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
     }
     const int g = lane >> 4;
     float2* so = (float2*)A.spin_out;
@@ -658,13 +679,25 @@ static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsampl
     return (A.g.Vh + 63) / 64 <= 2048;
 }
 
+// The bf16-feature layers (the learned preconditioner's network) with links as float16 codes.
+static wd_status mfma_hf16(wd_context ctx, const PTArgs& A, int cin, int cout, bool split, dim3 grid, dim3 block)
+{
+    if (split) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, true, true>), grid, block, 0, ctx->stream, A);
+    else if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 4, 8, true, false, true, false, true>), grid, block, 0, ctx->stream, A);
+    else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 8, false, false, true, false, true>), grid, block, 0, ctx->stream, A);
+    else hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, false, true>), grid, block, 0, ctx->stream, A);
+    WD_LAUNCHED();
+    return WD_OK;
+}
+
 template <int R>
-static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples, bool hf)
+static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples, bool hf, bool l16)
 {
     const bool split = ptconv_split(A, hf, cin, cout, nsamples);
     const int waves = (A.out_sites > A.g.Vh || split ? 2 : 1) * ((A.g.Vh + 63) / 64);
     dim3 grid((waves + 3) / 4, nsamples), block(256);
     const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
+    if (l16) return mfma_hf16(ctx, A, cin, cout, split, grid, block);
     if (split) {
         hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true, true>), grid, block, 0, ctx->stream, A);
     } else if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
@@ -741,8 +774,14 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
                   "a zero odd input half and even outputs only");
         return WD_EINVAL;
     }
+    // The bf16-feature layers read the links as float16 codes (12 reals): the entries of an SU(3)
+    // matrix are bounded by 1, so float16 keeps 2^-11 of them, below the bf16 rounding (2^-9) of
+    // the transported features the layer applies anyway, in half the bytes of float32 links.
+    // WD_PTCONV_LINKS32=1 keeps float32 links.
+    const bool l16 = half_feat && g->recon == 12 && use_mfma(wprec, cin, cout) &&
+                     !(getenv("WD_PTCONV_LINKS32") && atoi(getenv("WD_PTCONV_LINKS32")) != 0);
     const void* links;
-    WD_TRY(gauge_links(g, WD_F32, &links));
+    WD_TRY(gauge_links(g, l16 ? WD_F16 : WD_F32, &links));
     PTArgs A;
     A.gauge = (const char*)links;
     A.in = (const float2*)in;
@@ -768,7 +807,8 @@ wd_status ptconv_fwd(wd_gauge g, int cin, int cout, int wprec, const void* W, co
     }
     const bool r12 = g->recon == 12;
     if (use_mfma(wprec, cin, cout))
-        return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples, half_feat) : mfma_r<18>(g->ctx, A, cin, cout, nsamples, half_feat);
+        return r12 ? mfma_r<12>(g->ctx, A, cin, cout, nsamples, half_feat, l16)
+                   : mfma_r<18>(g->ctx, A, cin, cout, nsamples, half_feat, false);
     switch (wprec) {
     case WD_F32: return r12 ? fwd_r_w<12, P_F32>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F32>(g->ctx, A, cout, nsamples);
     case WD_F16: return r12 ? fwd_r_w<12, P_F16>(g->ctx, A, cout, nsamples) : fwd_r_w<18, P_F16>(g->ctx, A, cout, nsamples);
