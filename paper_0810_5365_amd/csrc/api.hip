@@ -378,7 +378,12 @@ wd_status wd_context_create(int device, void* stream, wd_context* out)
         delete c;
         return WD_ENOMEM;
     }
+    // kernels write reduction results straight into the mapped host buffer; without a device
+    // address for it (or with WD_RESULTS_UNMAPPED=1) they are copied behind the kernels and the
+    // host synchronises the stream instead of spinning on the buffer
     if (hipHostGetDevicePointer((void**)&c->hres_dev, c->hres, 0) != hipSuccess) c->hres_dev = nullptr;
+    if (const char* e = getenv("WD_RESULTS_UNMAPPED"))
+        if (atoi(e) != 0) c->hres_dev = nullptr;
     wd_status s = ensure_reduction(c, 4 * 2048);
     if (s != WD_OK) {
         hipFree(c->dres);
