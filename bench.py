@@ -588,7 +588,7 @@ def network_apply_times(w, ctx, net, dims, reps=100):
     ptrs = (ctypes.c_void_p * len(ws))(*[t.data_ptr() for t in ws])
     run = lambda: w.wd_ptnet_apply_even(f.g.handle, len(ws), widths, ptrs, net.wprec, fin.data_ptr(), fout.data_ptr())
     res = {}
-    for mode, env in (("bf16_hidden", {}), ("bf16_hidden_last_layer_unsplit", {"WD_PTCONV_SPLIT": "0"}),
+    for mode, env in (("bf16_hidden", {}), ("bf16_hidden_unsplit", {"WD_PTCONV_SPLIT": "0"}),
                       ("f32_hidden", {"WD_PTNET_F32_FEATURES": "1"})):
         os.environ.update(env)
         med, mn = timed_repeats(run, stream, torch, n=reps)

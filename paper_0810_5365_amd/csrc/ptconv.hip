@@ -557,7 +557,7 @@ __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int p
 
 // SIN / SOUT: the input / output is an EVEN spinor half field (A.spin_in / A.spin_out);
 // HF: the feature tensors hold bf16 pairs (one sample).
-// SPLIT (even outputs only, no zero parity): two waves share each 64-site group, the first
+// SPLIT (no zero parity): two waves share each 64-site group, the first
 // taking the stay path and the forward hops, the second the backward hops; the second's
 // accumulators are added to the first's through LDS.  With few sites (one wave per SIMD
 // otherwise) this halves each wave's chain of dependent path loads.
@@ -668,13 +668,14 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     }
 }
 
-// Split the nine paths of each 64-site group over two waves (the last layer of the learned
-// preconditioner: even outputs only) when the unsplit launch would give the chip at most one
-// round of two waves per SIMD (1024 SIMDs); WD_PTCONV_SPLIT = 0 / 1 forces it off / on.
+// Split the nine paths of each 64-site group over two waves (the 8 -> 8 hidden layers and the
+// 8 -> 4 last layer of the learned preconditioner) when the unsplit launch would give the chip
+// at most one round of two waves per SIMD (1024 SIMDs); WD_PTCONV_SPLIT = 0 / 1 forces it off / on.
 static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsamples)
 {
-    if (!(hf && cin == 8 && cout == 4 && A.spin_out && A.out_sites == A.g.Vh && A.zero_par < 0 && nsamples == 1))
-        return false;
+    const bool last = cin == 8 && cout == 4 && A.spin_out && A.out_sites == A.g.Vh;
+    const bool hidden = cin == 8 && cout == 8 && A.out_sites == 2 * A.g.Vh;   // both parities
+    if (!(hf && (last || hidden) && A.zero_par < 0 && nsamples == 1)) return false;
     if (const char* e = getenv("WD_PTCONV_SPLIT")) return atoi(e) != 0;
     return (A.g.Vh + 63) / 64 <= 2048;
 }
@@ -682,7 +683,8 @@ static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsampl
 // The bf16-feature layers (the learned preconditioner's network) with links as float16 codes.
 static wd_status mfma_hf16(wd_context ctx, const PTArgs& A, int cin, int cout, bool split, dim3 grid, dim3 block)
 {
-    if (split) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, true, true>), grid, block, 0, ctx->stream, A);
+    if (split && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 8, false, false, true, true, true>), grid, block, 0, ctx->stream, A);
+    else if (split) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, true, true>), grid, block, 0, ctx->stream, A);
     else if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 4, 8, true, false, true, false, true>), grid, block, 0, ctx->stream, A);
     else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 8, false, false, true, false, true>), grid, block, 0, ctx->stream, A);
     else hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, false, true>), grid, block, 0, ctx->stream, A);
@@ -694,11 +696,14 @@ template <int R>
 static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int nsamples, bool hf, bool l16)
 {
     const bool split = ptconv_split(A, hf, cin, cout, nsamples);
-    const int waves = (A.out_sites > A.g.Vh || split ? 2 : 1) * ((A.g.Vh + 63) / 64);
+    // one wave per 64-site group and parity computed, two when the group's paths are split
+    const int waves = (A.out_sites > A.g.Vh ? 2 : 1) * (split ? 2 : 1) * ((A.g.Vh + 63) / 64);
     dim3 grid((waves + 3) / 4, nsamples), block(256);
     const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
     if (l16) return mfma_hf16(ctx, A, cin, cout, split, grid, block);
-    if (split) {
+    if (split && cout == 8) {
+        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, true, true>), grid, block, 0, ctx->stream, A);
+    } else if (split) {
         hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true, true>), grid, block, 0, ctx->stream, A);
     } else if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
         if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, true, false>), grid, block, 0, ctx->stream, A);

@@ -7,6 +7,7 @@ and to supply the HIP stream.  If libwdirac.so is missing this module raises
 at import: there is no fallback path.
 """
 import ctypes
+import sys
 import os
 
 import numpy as np
@@ -197,6 +198,10 @@ class Context:
             self.handle = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be going away: the process
+        # releases the device memory itself, so nothing is called into the library then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -232,6 +237,10 @@ class Gauge:
             self.handle = None
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be going away: the process
+        # releases the device memory itself, so nothing is called into the library then
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
