@@ -422,7 +422,17 @@ template <int R, int CIN, bool L16 = false> struct MfRaw {
     uint4 h8;                                // L16: codes of reals 0..7
     uint2 h4;                                // L16: codes of reals 8..11
     float2 v[CIN][3];                        // neighbour features, channel b, colour k
+    uint4 hv[6];                             // bf16 features as loaded (see hf_plane), decoded at use
 };
+
+// bf16 hidden features (8 channels): per parity six planes of 16 bytes per site, four complex
+// numbers (bf16 pairs) each, in the order colour-major, channel-minor: complex (b, k) is word
+// b % 4 of plane 2 k + b / 4.  A lane loads its site's 24 complexes in six 16-byte loads, and an
+// accumulator tile's two channels of one colour are one 8-byte store.
+__device__ __forceinline__ size_t hf_plane(int par, int pl, int Vh, uint32_t cb)
+{
+    return (size_t)(par * 6 + pl) * Vh + cb;
+}
 
 // bf16 feature pair (re in the low half, as cvt_bf16x2 packs it) -> float2
 __device__ __forceinline__ float2 bf16x2_to_f2(uint32_t h)
@@ -430,8 +440,8 @@ __device__ __forceinline__ float2 bf16x2_to_f2(uint32_t h)
     return make_float2(__uint_as_float(h << 16), __uint_as_float(h & 0xffff0000u));
 }
 
-// HF: the feature tensors (input and output, where not a spinor) hold bf16 pairs, one
-// uint32 per complex at the float2 layout's index
+// HF: the feature tensors (input and output, where not a spinor) hold bf16 pairs in the
+// 16-byte planes of hf_plane
 template <int PATH, int R, int CIN, bool SIN, bool HF, bool L16>
 __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int par, uint32_t cb, const int c[4],
                                         MfRaw<R, CIN, L16>& x)
@@ -466,25 +476,23 @@ __device__ __forceinline__ void mf_load(const PTArgs& A, const float2* in, int p
         for (int b = 0; b < CIN; ++b)
 #pragma unroll
             for (int k = 0; k < 3; ++k) x.v[b][k] = sp[spin_f2(b, k, A.g.ps, src)];
-        return;
-    }
-    if constexpr (HF) {
-        const uint32_t* hs = (const uint32_t*)in + (size_t)spar * 3 * Vh + src;
+    } else if constexpr (HF) {
+        static_assert(CIN == 8, "bf16 hidden features have 8 channels");
+        const uint4* hp = (const uint4*)in;
+#pragma unroll
+        for (int pl = 0; pl < 6; ++pl) x.hv[pl] = hp[hf_plane(spar, pl, Vh, src)];
+    } else {
+        // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
+        const float2* site = in + (size_t)spar * 3 * Vh + src;
 #pragma unroll
         for (int b = 0; b < CIN; ++b)
 #pragma unroll
-            for (int k = 0; k < 3; ++k) x.v[b][k] = bf16x2_to_f2(hs[(size_t)(b * 6 + k) * Vh]);
-        return;
+            for (int k = 0; k < 3; ++k) x.v[b][k] = site[(size_t)(b * 6 + k) * Vh];
     }
-    // per-lane site offset once; the channel-plane offsets (b 6 + k) Vh are wave-uniform
-    const float2* site = in + (size_t)spar * 3 * Vh + src;
-#pragma unroll
-    for (int b = 0; b < CIN; ++b)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) x.v[b][k] = site[(size_t)(b * 6 + k) * Vh];
 }
 
-template <int PATH, int R, int CIN, bool L16>
+// HIN: the neighbour features arrived as bf16 planes (x.hv), else as float2 (x.v)
+template <int PATH, int R, int CIN, bool L16, bool HIN>
 __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int lane, uint16_t* B,
                                            const MfRaw<R, CIN, L16>& x, const bf16x4& Af, f32x4* acc)
 {
@@ -521,8 +529,16 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
         float v[6], t[6];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            v[2 * k] = x.v[b][k].x;
-            v[2 * k + 1] = x.v[b][k].y;
+            float2 q;
+            if constexpr (HIN) {
+                const uint4 h = x.hv[2 * k + (b >> 2)];
+                const uint32_t wd = (b & 3) == 0 ? h.x : (b & 3) == 1 ? h.y : (b & 3) == 2 ? h.z : h.w;
+                q = bf16x2_to_f2(wd);
+            } else {
+                q = x.v[b][k];
+            }
+            v[2 * k] = q.x;
+            v[2 * k + 1] = q.y;
         }
         if constexpr (PATH > 0) {
             mat_vec(u, v, t, PATH > 4);
@@ -551,7 +567,7 @@ __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int p
                                         MfRaw<R, CIN, L16>& nxt)
 {
     if constexpr (P < LAST) mf_load<P + 1, R, CIN, SIN, HF, L16>(A, in, par, cb, c, nxt);
-    mf_compute<P, R, CIN, L16>(A, c, lane, B, cur, Af[P], acc);
+    mf_compute<P, R, CIN, L16, HF && !SIN>(A, c, lane, B, cur, Af[P], acc);
     if constexpr (P < LAST) mf_pipe<P + 1, LAST, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, nxt, cur);
 }
 
@@ -636,7 +652,7 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
         for (int t = 0; t < 12; ++t) acc[t] += rs[t * 64 + lane];
     } else if (skip_hops) {
         mf_load<0, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
-        mf_compute<0, R, CIN, L16>(A, c, lane, B, ra, Af[0], acc);
+        mf_compute<0, R, CIN, L16, HF && !SIN>(A, c, lane, B, ra, Af[0], acc);
     } else if (skip_stay) {
         mf_load<1, R, CIN, SIN, HF, L16>(A, in, par, cb, c, ra);
         mf_pipe<1, 8, R, CIN, SIN, HF, L16>(A, in, par, cb, c, lane, B, Af, acc, ra, rb);
@@ -655,16 +671,15 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
         if constexpr (SOUT) {   // even outputs straight into the spinor half field
             if (2 * g < COUT) so[spin_f2(2 * g, k, A.g.ps, scb)] = make_float2(acc[t][0], acc[t][1]);
             if (2 * g + 1 < COUT) so[spin_f2(2 * g + 1, k, A.g.ps, scb)] = make_float2(acc[t][2], acc[t][3]);
-            continue;
+        } else if constexpr (HF) {   // channels 2 g, 2 g + 1 of colour k: words 2 (g % 2), + 1 of plane 2 k + g / 2
+            static_assert(COUT == 8, "bf16 hidden features have 8 channels");
+            uint2* ho = (uint2*)out;
+            ho[hf_plane(par, 2 * k + (g >> 1), Vh, scb) * 2 + (g & 1)] =
+                make_uint2(cvt_bf16x2(acc[t][0], acc[t][1]), cvt_bf16x2(acc[t][2], acc[t][3]));
+        } else {
+            if (2 * g < COUT) out[fidx(2 * g, par, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
+            if (2 * g + 1 < COUT) out[fidx(2 * g + 1, par, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
         }
-        if constexpr (HF) {
-            uint32_t* ho = (uint32_t*)out;
-            if (2 * g < COUT) ho[fidx(2 * g, par, k, Vh, scb)] = cvt_bf16x2(acc[t][0], acc[t][1]);
-            if (2 * g + 1 < COUT) ho[fidx(2 * g + 1, par, k, Vh, scb)] = cvt_bf16x2(acc[t][2], acc[t][3]);
-            continue;
-        }
-        if (2 * g < COUT) out[fidx(2 * g, par, k, Vh, scb)] = make_float2(acc[t][0], acc[t][1]);
-        if (2 * g + 1 < COUT) out[fidx(2 * g + 1, par, k, Vh, scb)] = make_float2(acc[t][2], acc[t][3]);
     }
 }
 
