@@ -12,7 +12,7 @@ events on the stream the kernels run on) and the FP64 CPU oracle timed on
 the host on the same operator.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--shape-sweep-only] [--precision-sweep-only]
-                    [--multi-rhs-only]
+                    [--multi-rhs-only] [--network-only]
 """
 import argparse
 import json
@@ -49,6 +49,8 @@ def parse():
                     help="only the EO dslash over lattices one extent short of 32^3 x 64 (for counter runs)")
     ap.add_argument("--multi-rhs-only", action="store_true",
                     help="only the 16-rhs records on 16^3 x 32 (per-rhs and matrix-core paths; for counter runs)")
+    ap.add_argument("--network-only", action="store_true",
+                    help="only the learned preconditioner's network applied on 32^3 x 64 and 16^3 x 32 (for counter runs)")
     ap.add_argument("--tune-cache", default=None,
                     help="JSON tuning table: loaded if it exists (no tuning), else tuned and written there")
     return ap.parse_args()
@@ -649,8 +651,7 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream(0)
     ctx = w.Context(0, stream.cuda_stream)
-    if args.multi_rhs_only:
-        rec = extras(w, ctx, stream, torch, ls, multi_rhs_only=True)
+    def copy_reference():
         # a 2 GiB copy (read and write), the reference for hardware byte counters in the same run
         src = torch.ones(1 << 31, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
@@ -658,7 +659,19 @@ def main():
             w.wd_device_copy(ctx.handle, src.data_ptr(), dst.data_ptr(), 1 << 31)
         torch.cuda.synchronize()
         del src, dst
+
+    if args.multi_rhs_only:
+        rec = extras(w, ctx, stream, torch, ls, multi_rhs_only=True)
+        copy_reference()
         print(json.dumps({"multi_rhs": rec}), flush=True)
+        ctx.close()
+        return
+    if args.network_only:
+        from paper_0810_5365_amd import learn
+        net = learn.load_net(learn.DEFAULT_WEIGHTS, w.BF16)
+        rec = {"x".join(map(str, d)): network_apply_times(w, ctx, net, d) for d in ((32, 32, 32, 64), (16, 16, 16, 32))}
+        copy_reference()
+        print(json.dumps({"network_apply_even": rec}), flush=True)
         ctx.close()
         return
 

@@ -519,7 +519,8 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
         } else {
             reconstruct_row2(u);
         }
-        // boundary sign folded into the (reconstructed) link: 18 products instead of 6 C_in
+        // boundary sign folded into the (reconstructed) link: 18 products instead of 6 C_in (a
+        // branch that skips them where the sign is +1 measured 0.6% slower at 32^3 x 64)
         const float sign = on_boundary<MU, FWD>(A.g, c) ? A.g.bcf[MU] : 1.0f;
 #pragma unroll
         for (int i = 0; i < 18; ++i) u[i] *= sign;
@@ -683,14 +684,14 @@ __global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
     }
 }
 
-// Split the nine paths of each 64-site group over two waves (the 8 -> 8 hidden layers and the
-// 8 -> 4 last layer of the learned preconditioner) when the unsplit launch would give the chip
-// at most one round of two waves per SIMD (1024 SIMDs); WD_PTCONV_SPLIT = 0 / 1 forces it off / on.
+// Split the nine paths of each 64-site group over two waves (the last layer of the learned
+// preconditioner: even outputs only) when the unsplit launch would give the chip at most one
+// round of two waves per SIMD (1024 SIMDs); WD_PTCONV_SPLIT = 0 / 1 forces it off / on.  The
+// 8 -> 8 layers are bound by their vector arithmetic, where more waves do not help.
 static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsamples)
 {
-    const bool last = cin == 8 && cout == 4 && A.spin_out && A.out_sites == A.g.Vh;
-    const bool hidden = cin == 8 && cout == 8 && A.out_sites == 2 * A.g.Vh;   // both parities
-    if (!(hf && (last || hidden) && A.zero_par < 0 && nsamples == 1)) return false;
+    if (!(hf && cin == 8 && cout == 4 && A.spin_out && A.out_sites == A.g.Vh && A.zero_par < 0 && nsamples == 1))
+        return false;
     if (const char* e = getenv("WD_PTCONV_SPLIT")) return atoi(e) != 0;
     return (A.g.Vh + 63) / 64 <= 2048;
 }
@@ -698,8 +699,7 @@ static bool ptconv_split(const PTArgs& A, bool hf, int cin, int cout, int nsampl
 // The bf16-feature layers (the learned preconditioner's network) with links as float16 codes.
 static wd_status mfma_hf16(wd_context ctx, const PTArgs& A, int cin, int cout, bool split, dim3 grid, dim3 block)
 {
-    if (split && cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 8, false, false, true, true, true>), grid, block, 0, ctx->stream, A);
-    else if (split) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, true, true>), grid, block, 0, ctx->stream, A);
+    if (split) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, true, true>), grid, block, 0, ctx->stream, A);
     else if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 4, 8, true, false, true, false, true>), grid, block, 0, ctx->stream, A);
     else if (cout == 8) hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 8, false, false, true, false, true>), grid, block, 0, ctx->stream, A);
     else hipLaunchKernelGGL((ptconv_mfma_kernel<12, 8, 4, false, true, true, false, true>), grid, block, 0, ctx->stream, A);
@@ -716,9 +716,7 @@ static wd_status mfma_r(wd_context ctx, const PTArgs& A, int cin, int cout, int 
     dim3 grid((waves + 3) / 4, nsamples), block(256);
     const bool si = A.spin_in != nullptr, so = A.spin_out != nullptr;
     if (l16) return mfma_hf16(ctx, A, cin, cout, split, grid, block);
-    if (split && cout == 8) {
-        hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 8, false, false, true, true>), grid, block, 0, ctx->stream, A);
-    } else if (split) {
+    if (split) {
         hipLaunchKernelGGL((ptconv_mfma_kernel<R, 8, 4, false, true, true, true>), grid, block, 0, ctx->stream, A);
     } else if (hf) {   // the 8-wide hidden layers of a 4 -> 8 -> ... -> 8 -> 4 network (checked by the caller)
         if (cin == 4) hipLaunchKernelGGL((ptconv_mfma_kernel<R, 4, 8, true, false, true, false>), grid, block, 0, ctx->stream, A);
