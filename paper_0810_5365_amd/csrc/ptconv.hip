@@ -579,8 +579,12 @@ __device__ __forceinline__ void mf_pipe(const PTArgs& A, const float2* in, int p
 // accumulators are added to the first's through LDS.  With few sites (one wave per SIMD
 // otherwise) this halves each wave's chain of dependent path loads.
 // L16: links read as float16 codes (A.gauge holds the 16-bit 12-real layout).
+// The first layer of the bf16-feature network (4 input channels: latency-bound, a third of
+// the VALU issue rate) runs three waves per SIMD (168 VGPRs, a few spilled): 3% less time per
+// application at 32^3 x 64; the other layers keep two (with three the last one spills 24
+// VGPRs and is slower).
 template <int R, int CIN, int COUT, bool SIN, bool SOUT, bool HF, bool SPLIT, bool L16 = false>
-__global__ void __launch_bounds__(256, 2) ptconv_mfma_kernel(PTArgs A)
+__global__ void __launch_bounds__(256, CIN == 4 && HF ? 3 : 2) ptconv_mfma_kernel(PTArgs A)
 {
     __shared__ __attribute__((aligned(16))) uint16_t lds[4][192 * MF_LD];
     __shared__ f32x4 red[SPLIT ? 2 : 1][SPLIT ? 12 * 64 : 1];
