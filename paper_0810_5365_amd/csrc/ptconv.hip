@@ -525,31 +525,65 @@ __device__ __forceinline__ void mf_compute(const PTArgs& A, const int c[4], int 
 #pragma unroll
         for (int i = 0; i < 18; ++i) u[i] *= sign;
     }
+    if constexpr (HIN) {
+        // bf16 features in: the stay path stages them as they are; a hop transports them with
+        // the link rounded to bf16 pairs, (Re, -Im) and (Im, Re) of each entry of U (U^dag for a
+        // backward hop), so that each complex product-sum is two bf16 dot products accumulated
+        // in float32 (v_dot2c_f32_bf16) instead of four FMAs on decoded values
+        auto word = [&](int b, int k) -> uint32_t {
+            const uint4 h = x.hv[2 * k + (b >> 2)];
+            return (b & 3) == 0 ? h.x : (b & 3) == 1 ? h.y : (b & 3) == 2 ? h.z : h.w;
+        };
+        if constexpr (PATH == 0) {
 #pragma unroll
-    for (int b = 0; b < CIN; ++b) {
-        float v[6], t[6];
+            for (int b = 0; b < CIN; ++b)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            float2 q;
-            if constexpr (HIN) {
-                const uint4 h = x.hv[2 * k + (b >> 2)];
-                const uint32_t wd = (b & 3) == 0 ? h.x : (b & 3) == 1 ? h.y : (b & 3) == 2 ? h.z : h.w;
-                q = bf16x2_to_f2(wd);
-            } else {
-                q = x.v[b][k];
-            }
-            v[2 * k] = q.x;
-            v[2 * k + 1] = q.y;
-        }
-        if constexpr (PATH > 0) {
-            mat_vec(u, v, t, PATH > 4);
+                for (int k = 0; k < 3; ++k) *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = word(b, k);
         } else {
+            constexpr bool DAG = PATH > 4;
+            bf16x2_t pre[9], pim[9];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) t[i] = v[i];
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int c2 = 0; c2 < 3; ++c2) {
+                    const int e = DAG ? 3 * c2 + a : 3 * a + c2;
+                    const float ur = u[2 * e], ui = DAG ? -u[2 * e + 1] : u[2 * e + 1];
+                    pre[3 * a + c2] = __builtin_bit_cast(bf16x2_t, cvt_bf16x2(ur, -ui));
+                    pim[3 * a + c2] = __builtin_bit_cast(bf16x2_t, cvt_bf16x2(ui, ur));
+                }
+#pragma unroll
+            for (int b = 0; b < CIN; ++b)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    float re = 0.f, im = 0.f;
+#pragma unroll
+                    for (int c2 = 0; c2 < 3; ++c2) {
+                        const bf16x2_t f = __builtin_bit_cast(bf16x2_t, word(b, c2));
+                        re = __builtin_amdgcn_fdot2_f32_bf16(pre[3 * a + c2], f, re, false);
+                        im = __builtin_amdgcn_fdot2_f32_bf16(pim[3 * a + c2], f, im, false);
+                    }
+                    *(uint32_t*)&B[(a * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(re, im);
+                }
         }
+    } else {
 #pragma unroll
-        for (int k = 0; k < 3; ++k)
-            *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(t[2 * k], t[2 * k + 1]);
+        for (int b = 0; b < CIN; ++b) {
+            float v[6], t[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                v[2 * k] = x.v[b][k].x;
+                v[2 * k + 1] = x.v[b][k].y;
+            }
+            if constexpr (PATH > 0) {
+                mat_vec(u, v, t, PATH > 4);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) t[i] = v[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                *(uint32_t*)&B[(k * 64 + lane) * MF_LD + 2 * b] = cvt_bf16x2(t[2 * k], t[2 * k + 1]);
+        }
     }
     wave_lds_sync();
 #pragma unroll
