@@ -70,6 +70,10 @@ wd_status dslash_setup(const Geom& g, const DslashCall& c, const TuneParam& tp, 
     A.g = g;
     A.par = c.par;
     A.remap = tp.remap;
+    {   // the fused update's x is loaded non-temporally; WD_DSLASH_XNT=0 turns that off
+        static const int xnt = getenv("WD_DSLASH_XNT") ? (atoi(getenv("WD_DSLASH_XNT")) != 0) : 1;
+        A.xnt = xnt;
+    }
     A.rhs_inner = (tp.rhs_inner && c.nrhs > 1) ? c.nrhs : 0;
     A.gf = c.gf;
     A.zb = 0;

@@ -44,6 +44,7 @@ struct DslashArgs {
     double* red;     // per-workgroup partial sums of a fused reduction (dslash_red.hip)
     const char* y;   // the other operand of the fused <y, out>
     const double* coef;   // RED_CGR: the step length alpha, in device memory
+    int xnt;              // fused update: load x non-temporally
 };
 
 // Kernel arguments for a launch of the hopping term with launch shape tp (dslash.hip).
@@ -219,7 +220,10 @@ __device__ __forceinline__ void dslash_site(const DslashArgs& A, uint32_t cb, co
     const T b = (T)A.b;
     T xv[24];
     if constexpr (XPAY) {
-        SpinorIO<P>::load(A.x + rhs * A.x_stride, A.g.ps, cb, xv);
+        // x is read once, at the site written: a non-temporal load leaves the last-level cache
+        // to the fields the next launch reads (measured: 0.75% on the Mhat^dag Mhat step)
+        if (A.xnt) SpinorIO<P>::load_nt(A.x + rhs * A.x_stride, A.g.ps, cb, xv);
+        else SpinorIO<P>::load(A.x + rhs * A.x_stride, A.g.ps, cb, xv);
         const T a = (T)A.a;
 #pragma unroll
         for (int k = 0; k < 24; ++k) acc[k] = a * xv[k] + b * acc[k];

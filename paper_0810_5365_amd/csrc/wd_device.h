@@ -191,6 +191,17 @@ template <> struct SpinorIO<P_F32> {
 #pragma unroll
         for (int k = 0; k < 6; ++k) p[(size_t)k * Vh + cb] = make_float4(v[4 * k], v[4 * k + 1], v[4 * k + 2], v[4 * k + 3]);
     }
+    // non-temporal: a field read once, that the caches need not keep
+    __device__ __forceinline__ static void load_nt(const char* base, int Vh, uint32_t cb, float* v)
+    {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4* p = (const f4*)base;
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const f4 q = __builtin_nontemporal_load(p + (size_t)k * Vh + cb);
+            v[4 * k] = q.x; v[4 * k + 1] = q.y; v[4 * k + 2] = q.z; v[4 * k + 3] = q.w;
+        }
+    }
 };
 
 template <> struct SpinorIO<P_F64> {
@@ -210,6 +221,16 @@ template <> struct SpinorIO<P_F64> {
 #pragma unroll
         for (int k = 0; k < 12; ++k) p[(size_t)k * Vh + cb] = make_double2(v[2 * k], v[2 * k + 1]);
     }
+    __device__ __forceinline__ static void load_nt(const char* base, int Vh, uint32_t cb, double* v)
+    {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2* p = (const d2*)base;
+#pragma unroll
+        for (int k = 0; k < 12; ++k) {
+            const d2 q = __builtin_nontemporal_load(p + (size_t)k * Vh + cb);
+            v[2 * k] = q.x; v[2 * k + 1] = q.y;
+        }
+    }
 };
 
 template <int P> struct SpinorIO16 {
@@ -220,6 +241,17 @@ template <int P> struct SpinorIO16 {
         const float s = ((const float*)(p + (size_t)3 * Vh))[cb];
 #pragma unroll
         for (int k = 0; k < 3; ++k) unpack8<P>(p[(size_t)k * Vh + cb], s, v + 8 * k);
+    }
+    __device__ __forceinline__ static void load_nt(const char* base, int Vh, uint32_t cb, float* v)
+    {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        const u4* p = (const u4*)base;
+        const float s = __builtin_nontemporal_load((const float*)(p + (size_t)3 * Vh) + cb);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const u4 q = __builtin_nontemporal_load(p + (size_t)k * Vh + cb);
+            unpack8<P>(make_uint4(q.x, q.y, q.z, q.w), s, v + 8 * k);
+        }
     }
     // s = max |v_i|, codes RNE16(v_i * RN(1/s)); an all-zero site stores s = 0.
     __device__ __forceinline__ static void store(char* base, int Vh, uint32_t cb, const float* v)
