@@ -486,7 +486,7 @@ def solve_extras(w, ctx, torch, ls, dims=(32, 32, 32, 64), eps=0.6, kappa=0.1245
             d["operator_gflops_over_mdagm_kernel"] = round(gf / mdagm_gflops, 3)
     runs = [("f64", w.F64, False), ("f32", w.F32, False), ("f16", w.F16, False), ("bf16", w.BF16, False),
             ("pure_f32", w.F32, True)]
-    default_delta = {w.F32: 1e-4, w.F16: 1e-2, w.BF16: 3e-2}   # the library's defaults (delta < 0)
+    default_delta = {w.F32: 1e-5, w.F16: 1e-2, w.BF16: 3e-2}   # the library's defaults (delta < 0)
     for name, p, pure in runs:
         secs = []
         for rep in range(2):   # the first solve of a precision also sizes the workspace

@@ -225,11 +225,11 @@ typedef struct {
     int maxiter;       /* iteration cap; WD_ENOCONV when reached                   */
     int sloppy;        /* wd_prec of the inner iterations (F64, F32, F16, BF16)    */
     double delta;      /* reliable update when ||r|| < delta * max ||r|| since last;
-                          < 0: the default for the sloppy precision (F32 1e-4,
+                          < 0: the default for the sloppy precision (F32 1e-5,
                           F16 1e-2, BF16 3e-2; measured with CG and BiCGstab on
                           the 32^3 x 64 and 16^3 x 32 solves: 16-bit ~10x above
-                          where the iteration count starts to grow, F32 the
-                          smallest value swept, with no growth)                   */
+                          where the iteration count starts to grow, F32 ~170x
+                          the float32 unit roundoff, with no growth down to it) */
     int pure_sloppy;   /* 1: never recompute the residual (reports the stall level) */
 } wd_solver_params;
 

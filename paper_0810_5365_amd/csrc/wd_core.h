@@ -61,7 +61,7 @@ inline size_t half_bytes(const Geom& g, int p) { return spinor_site_bytes(p) * (
 // Reliable-update threshold: delta < 0 selects the default for the sloppy precision.
 inline double default_delta(int prec)
 {
-    return prec == WD_F32 ? 1e-4 : (prec == WD_F16 ? 1e-2 : (prec == WD_BF16 ? 3e-2 : 0.1));
+    return prec == WD_F32 ? 1e-5 : (prec == WD_F16 ? 1e-2 : (prec == WD_BF16 ? 3e-2 : 0.1));
 }
 inline double resolve_delta(double delta, int prec) { return delta < 0.0 ? default_delta(prec) : delta; }
 inline size_t halves_of(int subset, int nrhs) { return (size_t)nrhs * (subset == WD_FULL ? 2 : 1); }

@@ -197,10 +197,11 @@ class Context:
             wd_context_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be going away: the process
         # releases the device memory itself, so nothing is called into the library then
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals may already be None by then)
+        if self.handle is None or _finalizing():
             return
         try:
             self.close()
@@ -236,10 +237,11 @@ class Gauge:
             wd_gauge_destroy(self.handle)
             self.handle = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be going away: the process
         # releases the device memory itself, so nothing is called into the library then
-        if sys.is_finalizing():
+        # (the check is bound at definition: module globals may already be None by then)
+        if self.handle is None or _finalizing():
             return
         try:
             self.close()

@@ -294,7 +294,7 @@ def test_wilson_solve_full_system(w, ctx, sloppy):
     assert res <= 1.05 * tol, (res, info.as_dict())
 
 
-@pytest.mark.parametrize("sloppy,delta", [("f32", 0.1), ("f32", 1e-4), ("f16", -1.0), ("bf16", 0.1), ("bf16", -1.0)])
+@pytest.mark.parametrize("sloppy,delta", [("f32", 0.1), ("f32", 1e-4), ("f32", -1.0), ("f16", -1.0), ("bf16", 0.1), ("bf16", -1.0)])
 def test_cg_reliable_update_thresholds(w, ctx, sloppy, delta):
     """Explicit and default (delta < 0) reliable-update thresholds reach the FP64-checked
     tolerance; the number of updates falls as delta does."""
