@@ -238,7 +238,10 @@ typedef struct {
     int reliable_updates;   /* float64 residual recomputations                    */
     int operator_applies;   /* applications of the solved operator                */
     int status;             /* wd_status of the solve                             */
-    double true_resid;      /* ||b - A x|| / ||b|| in float64, A the solved operator */
+    double true_resid;      /* ||b - A x|| / ||b|| in float64, A the solved operator;
+                               the even-odd solvers of M x = b report the Schur
+                               system's ||bhat - Mhat x_e|| / ||b|| (their
+                               convergence test)                                  */
     double true_resid_M;    /* ||b - M x|| / ||b|| for wd_wilson_solve, else -1     */
     double seconds;         /* wall time from call to return                      */
     int cycles;             /* flexible GMRES: restart cycles (float64 residual updates) */
@@ -261,7 +264,8 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
  * x_o = b_o + kappa D_oe x_e.  b, x: FULL float64 packed fields.  Reports
  * ||b - M x|| / ||b|| in true_resid_M, evaluated in float64 on the even rows
  * (b_e - x_e + kappa D_eo x_o, with the x_o built); the odd rows are zero by the
- * construction of x_o, up to its float64 rounding.  Synchronous. */
+ * construction of x_o, up to its float64 rounding.  true_resid is the float64
+ * ||b'_e - Mhat x_e|| / ||b|| that decides convergence.  Synchronous. */
 wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
                           const void* b, void* x, wd_solver_info* info);
 

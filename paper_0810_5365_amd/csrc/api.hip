@@ -192,7 +192,7 @@ static int red_out_prec(int red, int prec)
 }
 
 wd_status op_M_red_partials(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out,
-                            int red, const void* y, const double* coef, int* nblk)
+                            int red, const void* y, const double* coef, int* nblk, void* hop_out)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -217,8 +217,8 @@ wd_status op_M_red_partials(wd_gauge g, double kappa, int subset, int dagger, in
         *nblk = n[0] + n[1];
         return WD_OK;
     }
-    void* tmp = nullptr;
-    WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
+    void* tmp = hop_out;
+    if (!tmp) WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
     const int par = subset == WD_EVEN ? 0 : 1;
     WD_TRY(hop_half(g, prec, 1 - par, dagger, 1, in, hb, tmp, hb, nullptr, 0, 0.0, 1.0));
     return launch_dslash_red(ctx, G, half_call(g, links, prec, par, dagger, 1, tmp, hb, out, hbo, in, hb, 1.0,
@@ -226,7 +226,7 @@ wd_status op_M_red_partials(wd_gauge g, double kappa, int subset, int dagger, in
 }
 
 wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, const void* in, void* out, int red,
-                   const void* y, int slot)
+                   const void* y, int slot, void* hop_out)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -236,11 +236,11 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, c
     WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
     if (subset == WD_FULL || red_values(red) == 1) {
         int n = 0;
-        WD_TRY(op_M_red_partials(g, kappa, subset, dagger, prec, in, out, red, y, nullptr, &n));
+        WD_TRY(op_M_red_partials(g, kappa, subset, dagger, prec, in, out, red, y, nullptr, &n, hop_out));
         return reduce_partials(ctx, n, 1, slot);
     }
-    void* tmp = nullptr;
-    WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
+    void* tmp = hop_out;
+    if (!tmp) WD_TRY(ws_get(ctx, "op_M.tmp", (size_t)hb, &tmp));
     const int par = subset == WD_EVEN ? 0 : 1;
     int n = 0;
     WD_TRY(hop_half(g, prec, 1 - par, dagger, 1, in, hb, tmp, hb, nullptr, 0, 0.0, 1.0));
@@ -249,7 +249,7 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, c
     return reduce_partials(ctx, n, red_values(red), slot);
 }
 
-wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr)
+wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr, const void* doe_xe)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -260,7 +260,13 @@ wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr
     WD_TRY(gauge_links(g, WD_F64, &links));
     WD_TRY(ensure_reduction(ctx, 3 * (((size_t)G.Vh + 63) / 64)));
     // x_o = b_o + kappa D_oe x_e
-    WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_e + hb, hb, b_e + hb, hb, 1.0, kappa));
+    if (doe_xe) {
+        const void* in[2] = {b_e + hb, doe_xe};
+        const double cr[2] = {1.0, kappa}, ci[2] = {0.0, 0.0};
+        WD_TRY(blas_lincomb(ctx, G, 1, WD_F64, 2, in, cr, ci, x_e + hb, nullptr, false));
+    } else {
+        WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_e + hb, hb, b_e + hb, hb, 1.0, kappa));
+    }
     // the even rows of b - M x: b_e - (x_e - kappa D_eo x_o), summed in float64 (the residual
     // itself is kept only in float32)
     void* t = nullptr;

@@ -13,8 +13,10 @@ namespace wd {
 
 typedef std::complex<double> cd;
 
+// doe_xe: set to a float64 half field holding D_oe x for the x returned, when one is at hand,
+// else to null.
 static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& prm, const void* bhat, double bnorm2,
-                              void* x, wd_solver_info* info)
+                              void* x, wd_solver_info* info, const void** doe_xe)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -30,12 +32,18 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     WD_TRY(ws_get(ctx, "bicg.s", hs, &s));
     WD_TRY(ws_get(ctx, "bicg.t", hs, &t));
     WD_TRY(ws_get(ctx, "bicg.xs", hs, &xs));
+    void* doe;
+    WD_TRY(ws_get(ctx, "bicg.doe", h64, &doe));
+    bool doe_at_x = false;   // doe holds D_oe x for the current x
+    *doe_xe = nullptr;
     const double target = prm.tol * prm.tol * bnorm2;
     auto true_res = [&](double* rr) -> wd_status {
-        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x, r, RED_RESID, bhat, 0));   // r = bhat - Mhat x, ||r||^2
+        // r = bhat - Mhat x, ||r||^2; D_oe x stays in doe
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x, r, RED_RESID, bhat, 0, doe));
         WD_TRY(fetch_results(ctx, 1));
         *rr = ctx->hres[0];
         info->operator_applies++;
+        doe_at_x = true;
         return WD_OK;
     };
     auto dot = [&](const void* a, const void* b, cd* out) -> wd_status {
@@ -121,6 +129,7 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         }
         if (rr_s <= target || rr_s < delta * delta * maxrr) {
             WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
+            doe_at_x = false;
             WD_TRY(blas_zero(ctx, G, 1, ps, xs));
             dirty = false;
             WD_TRY(true_res(&rr));
@@ -138,8 +147,10 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
     }
     if (dirty) {   // else rr is that of the last reliable update, already of this x
         WD_TRY(blas_axpby(ctx, G, 1, ps, xs, 1.0, WD_F64, x, 1.0));
+        doe_at_x = false;
         WD_TRY(true_res(&rr));
     }
+    if (doe_at_x) *doe_xe = doe;
     info->true_resid = std::sqrt(rr / bnorm2);
     // the recomputed float64 residual decides: converged is WD_OK even after a breakdown
     // (the iterate it left may already meet tol), non-finite is WD_ENAN
@@ -183,6 +194,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
     const double bb = ctx->hres[0];
     wd_status s = WD_OK;
+    const void* doe_xe = nullptr;   // D_oe x_e from the last float64 residual, if at hand
     if (!std::isfinite(bb)) {   // NaN or Inf in the source: nothing to iterate on
         set_error("wd_bicgstab_solve: the source holds NaN or Inf");
         info->true_resid = info->true_resid_M = bb;
@@ -192,13 +204,13 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
         return WD_ENAN;
     }
     if (bb > 0.0) {
-        s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info);
+        s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info, &doe_xe);
         if (s != WD_OK && s != WD_ENOCONV) return s;
     } else {
         WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
     }
     double rr_full;
-    WD_TRY(eo_finish(g, kappa, b, x, &rr_full));   // x_o, then ||b - M x||^2 in float64
+    WD_TRY(eo_finish(g, kappa, b, x, &rr_full, doe_xe));   // x_o, then ||b - M x||^2 in float64
     info->true_resid_M = bb > 0 ? std::sqrt(rr_full / bb) : 0.0;
     info->operator_applies++;
     info->status = s;

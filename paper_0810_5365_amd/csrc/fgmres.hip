@@ -125,15 +125,20 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
     // rows of b - M x vanish and the even rows equal bhat - Mhat x_e (bhat = b_e + kappa D_eo b_o):
     // so the float64 refinement only needs the Schur residual (two hops per cycle).
     WD_TRY(hop_half(g, WD_F64, 0, 0, 1, b_o, (long long)h64, bhat, (long long)h64, b_e, (long long)h64, 1.0, kappa));
+    void* doe;   // D_oe x_e of the last Schur residual, reused for x_o at the end
+    WD_TRY(ws_get(ctx, "fgm.doe", h64, &doe));
+    bool doe_at_x = false;   // doe holds D_oe x_e for the current x_e
     auto schur_res = [&](double* rr) -> wd_status {
-        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x_e, rhat, RED_RESID, bhat, 0));   // rhat = bhat - Mhat x_e
+        // rhat = bhat - Mhat x_e
+        WD_TRY(op_M_red(g, kappa, WD_EVEN, 0, WD_F64, x_e, rhat, RED_RESID, bhat, 0, doe));
         WD_TRY(fetch_results(ctx, 1));
         *rr = ctx->hres[0];
         info->operator_applies++;
+        doe_at_x = true;
         return WD_OK;
     };
     auto finish_x = [&](double* rr) -> wd_status {   // x_o, then the full residual in float64
-        WD_TRY(eo_finish(g, kappa, b, x, rr));
+        WD_TRY(eo_finish(g, kappa, b, x, rr, doe_at_x ? doe : nullptr));
         info->operator_applies++;
         return WD_OK;
     };
@@ -257,6 +262,7 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         // x_e += e_e (float64), then the new Schur residual
         WD_TRY(launch_convert(ctx, G, nh, WD_F32, e, WD_F64, e64));
         WD_TRY(blas_axpby(ctx, G, nh, WD_F64, e64, 1.0, WD_F64, x_e, 1.0));
+        doe_at_x = false;
         const double rr_prev = rr;
         WD_TRY(schur_res(&rr));
         info->reliable_updates++;

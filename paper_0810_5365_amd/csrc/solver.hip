@@ -90,28 +90,39 @@ static wd_status residual_general(const CGProblem& P, int pacc, const void* x, v
 }
 
 // Wilson system: t = bhat - Mhat x in float64, kept at the accumulation precision, with ww =
-// ||t||^2 (two float64 launches), then rs = Mhat^dag t with rr = ||rs||^2 at that precision.
-// Mhat^dag (bhat - Mhat x) is the normal-equation residual c - A x: the cancellation happens in
-// the float64 difference, and the operator applied to that small vector only needs the
-// precision rs is kept in.  With x_zero the first step is a conversion of bhat.
-static wd_status residual_wilson(const CGProblem& P, int pacc, const void* x, bool x_zero, void* rs, double* rr,
-                                 double* ww)
+// ||t||^2 (two float64 launches; D_oe x stays in doe), then rs = Mhat^dag t with rr = ||rs||^2 at
+// that precision.  Mhat^dag (bhat - Mhat x) is the normal-equation residual c - A x: the
+// cancellation happens in the float64 difference, and the operator applied to that small vector
+// only needs the precision rs is kept in.  With x_zero the first step is a conversion of bhat.
+// need_rs: RS_ALWAYS queues both parts before waiting; RS_UNLESS_DONE reads ww first and skips
+// rs when ww <= stop_w (the solve ends there); RS_NEVER computes ww only.  *rs_done tells whether
+// rs and rr were formed.
+enum { RS_ALWAYS, RS_UNLESS_DONE, RS_NEVER };
+static wd_status residual_wilson(const CGProblem& P, int pacc, const void* x, bool x_zero, void* rs, void* doe,
+                                 double* rr, double* ww, int need_rs, double stop_w, bool* rs_done)
 {
     wd_context ctx = P.g->ctx;
     const Geom& G = P.g->geom;
     void* t;
     WD_TRY(ws_get(ctx, "cg.t", half_bytes(G, pacc), &t));
+    *rs_done = false;
     if (x_zero) {
         WD_TRY(launch_convert(ctx, G, 1, WD_F64, P.bhat, pacc, t));
-        WD_TRY(blas_norm2(ctx, G, 1, WD_F64, P.bhat, true));
-        *ww = ctx->hres[0];
+        WD_TRY(blas_norm2(ctx, G, 1, WD_F64, P.bhat, true));   // slot 0
     } else {
-        WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, WD_F64, x, t, pacc == WD_F64 ? RED_RESID : RED_RESLO, P.bhat, 1));
+        WD_TRY(op_M_red(P.g, P.kappa, P.subset, 0, WD_F64, x, t, pacc == WD_F64 ? RED_RESID : RED_RESLO, P.bhat, 0,
+                        doe));
+        if (need_rs != RS_ALWAYS) {
+            WD_TRY(fetch_results(ctx, 1));
+            *ww = ctx->hres[0];
+            if (need_rs == RS_NEVER || *ww <= stop_w) return WD_OK;
+        }
     }
-    WD_TRY(op_M_red(P.g, P.kappa, P.subset, 1, pacc, t, rs, RED_NORM, nullptr, 0));
+    WD_TRY(op_M_red(P.g, P.kappa, P.subset, 1, pacc, t, rs, RED_NORM, nullptr, 1));
     WD_TRY(fetch_results(ctx, 2));
-    *rr = ctx->hres[0];
-    if (!x_zero) *ww = ctx->hres[1];
+    *ww = ctx->hres[0];
+    *rr = ctx->hres[1];
+    *rs_done = true;
     return WD_OK;
 }
 
@@ -125,7 +136,10 @@ static wd_status residual_wilson(const CGProblem& P, int pacc, const void* x, bo
 // behind it.  When rr_new calls for a reliable update, xs
 // already holds alpha p: x += xs in float64, the residual is recomputed from x and p' is formed
 // again from the old p (still in its buffer) with beta = rr / rr_s.
-static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x, wd_solver_info* info)
+// doe_xe (Wilson system, may be null): set to a float64 half field holding D_oe x for the x
+// returned, when one is at hand, else to null.
+static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x, wd_solver_info* info,
+                        const void** doe_xe = nullptr)
 {
     wd_context ctx = P.g->ctx;
     const Geom& G = P.g->geom;
@@ -144,6 +158,10 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     WD_TRY(ws_get(ctx, "cg.p", half_bytes(G, pop) * nh, &pa));
     WD_TRY(ws_get(ctx, "cg.p2", half_bytes(G, pop) * nh, &pb));
     WD_TRY(ws_get(ctx, "cg.mp", half_bytes(G, pop) * nh, &mp));
+    void* doe = nullptr;
+    if (wilson) WD_TRY(ws_get(ctx, "cg.doe", half_bytes(G, WD_F64), &doe));
+    bool doe_at_x = false;   // doe holds D_oe x for the current x
+    if (doe_xe) *doe_xe = nullptr;
     *info = wd_solver_info{};
     std::vector<double> alphas, betas;   // for the Ritz-value estimates
 
@@ -152,7 +170,8 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     const bool x_zero = is_zero_f64(ctx, G, nh, x);
     double cc, rr = 0.0, ww = -1.0;
     if (wilson) {
-        WD_TRY(residual_wilson(P, pacc, nullptr, true, rs, &cc, &ww));
+        bool rs_done;
+        WD_TRY(residual_wilson(P, pacc, nullptr, true, rs, doe, &cc, &ww, RS_ALWAYS, 0.0, &rs_done));
         if (!std::isfinite(ww)) cc = ww;
     } else {
         WD_TRY(blas_norm2(ctx, G, nh, WD_F64, P.c, true));
@@ -176,16 +195,20 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
         return WD_OK;
     }
 
-    // residual of the current x into rs (with rr, and ww for the Wilson system)
-    auto residual = [&]() -> wd_status {
-        if (wilson) return residual_wilson(P, pacc, x, false, rs, &rr, &ww);
-        return residual_general(P, pacc, x, r, rs, &rr);
+    // residual of the current x into rs (with rr, and ww for the Wilson system); for the Wilson
+    // system need_rs says when rs may be left out (see residual_wilson)
+    auto residual = [&](int need_rs) -> wd_status {
+        if (!wilson) return residual_general(P, pacc, x, r, rs, &rr);
+        bool rs_done;
+        WD_TRY(residual_wilson(P, pacc, x, false, rs, doe, &rr, &ww, need_rs, target_w, &rs_done));
+        doe_at_x = true;
+        return WD_OK;
     };
     if (x_zero) {   // the residual is c itself, already at hand
         rr = cc;
         if (!wilson) WD_TRY(launch_convert(ctx, G, nh, WD_F64, P.c, pacc, rs));
     } else {
-        WD_TRY(residual());
+        WD_TRY(residual(RS_ALWAYS));
         info->operator_applies++;
     }
     auto converged = [&]() { return wilson ? ww <= target_w : rr <= target_r; };
@@ -236,9 +259,12 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
             if (done_sloppy || reliable) {
                 WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
                 xs_live = false;
+                doe_at_x = false;
                 if (done_sloppy) break;
-                // reliable update: the residual recomputed from x, the recurrence restarted from it
-                WD_TRY(residual());
+                // reliable update: the residual recomputed from x, the recurrence restarted from it;
+                // when the sloppy residual says the target is reached, the float64 norm is read
+                // before the rest is queued, which a converged solve no longer needs
+                WD_TRY(residual(rr_new <= trigger ? RS_UNLESS_DONE : RS_ALWAYS));
                 stale = false;
                 info->operator_applies++;
                 info->reliable_updates++;
@@ -261,13 +287,19 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
             rr_s = rr_new;
         }
     }
-    if (xs_live) WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+    if (xs_live) {
+        WD_TRY(blas_axpby(ctx, G, nh, pacc, xs, 1.0, WD_F64, x, 1.0));
+        doe_at_x = false;
+    }
     if (stale) {   // else rr, ww are those of the last reliable update, already of this x
-        WD_TRY(residual());
+        WD_TRY(residual(RS_NEVER));
         info->operator_applies++;
     }
-    info->true_resid = std::sqrt(rr / cc);
+    // the Wilson system reports the float64 residual its convergence test uses,
+    // ||bhat - Mhat x|| / ||b||; the general system ||c - A x|| / ||c||
+    info->true_resid = wilson ? std::sqrt(ww / P.wnorm2) : std::sqrt(rr / cc);
     info->true_resid_M = wilson ? std::sqrt(ww / P.wnorm2) : -1.0;
+    if (doe_xe && wilson && doe_at_x) *doe_xe = doe;
     if (status != WD_ENAN) cg_ritz_extremes(alphas, betas, &info->lambda_min, &info->lambda_max);
     if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
     if (status == WD_ENOCONV)
@@ -349,11 +381,12 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     WD_TRY(blas_norm2(ctx, G, 2, WD_F64, b, true));
     const double bb = ctx->hres[0];
     CGProblem P{g, kappa, WD_EVEN, nullptr, bhat, bb};
-    wd_status s = cg_run(P, *params, x_e, info);
+    const void* doe_xe = nullptr;   // D_oe x_e from the last float64 residual, if at hand
+    wd_status s = cg_run(P, *params, x_e, info, &doe_xe);
     if (s != WD_OK && s != WD_ENOCONV) return s;
     // x_o, then the full-system residual in float64
     double rr;
-    WD_TRY(eo_finish(g, kappa, b, x, &rr));
+    WD_TRY(eo_finish(g, kappa, b, x, &rr, doe_xe));
     info->true_resid_M = bb > 0 ? std::sqrt(rr / bb) : 0.0;
     info->operator_applies++;
     hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
