@@ -236,7 +236,8 @@ typedef struct {
 typedef struct {
     int iters;              /* CG iterations                                      */
     int reliable_updates;   /* float64 residual recomputations                    */
-    int operator_applies;   /* applications of the solved operator                */
+    int operator_applies;   /* applications of the solved operator, float64
+                               residual checks included (one each)                 */
     int status;             /* wd_status of the solve                             */
     double true_resid;      /* ||b - A x|| / ||b|| in float64, A the solved operator;
                                the even-odd solvers of M x = b report the Schur
@@ -252,6 +253,9 @@ typedef struct {
                                ends of its spectrum, lambda_min from above, lambda_max
                                from below.  0 where not computed (other solvers, a
                                breakdown, or no iteration).                           */
+    long long hops;         /* hopping-term applications D_eo / D_oe on one parity
+                               (float64 ones included) over the whole call: the
+                               operator work of the solve, 4 per Mhat^dag Mhat     */
 } wd_solver_info;
 
 /* Solve A x = b, A = M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD), by CG.
@@ -262,10 +266,14 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
 /* Solve M x = b on the full lattice through the even-odd Schur complement:
  * b'_e = b_e + kappa D_eo b_o, CG on Mhat^dagger Mhat x_e = Mhat^dagger b'_e,
  * x_o = b_o + kappa D_oe x_e.  b, x: FULL float64 packed fields.  Reports
- * ||b - M x|| / ||b|| in true_resid_M, evaluated in float64 on the even rows
- * (b_e - x_e + kappa D_eo x_o, with the x_o built); the odd rows are zero by the
- * construction of x_o, up to its float64 rounding.  true_resid is the float64
- * ||b'_e - Mhat x_e|| / ||b|| that decides convergence.  Synchronous. */
+ * ||b - M x|| / ||b|| in true_resid_M, in float64: the odd rows are zero by the
+ * construction of x_o, up to its float64 rounding, and the even rows
+ * b_e - x_e + kappa D_eo x_o equal b'_e - Mhat x_e.  When x_o is built from the
+ * D_oe x_e of the solver's last float64 Schur residual (taken at the returned
+ * x_e: a converged or capped solve, or a non-zero guess) that residual is the
+ * even rows; otherwise one more float64 launch evaluates them with the x_o
+ * built.  true_resid is the float64 ||b'_e - Mhat x_e|| / ||b|| that decides
+ * convergence.  Synchronous. */
 wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* params,
                           const void* b, void* x, wd_solver_info* info);
 
@@ -342,7 +350,7 @@ wd_status wd_device_copy(wd_context ctx, const void* src, void* dst, size_t byte
  * or 16-bit with the per-site scale; arithmetic in float32, float64 for F64);
  * reliable updates recompute bhat - Mhat x in float64 when the iterated
  * residual drops below delta times its running maximum.  true_resid is ||bhat - Mhat x_e|| / ||b||,
- * true_resid_M the full-system ||b - M x|| / ||b|| (float64, even rows evaluated as
+ * true_resid_M the full-system ||b - M x|| / ||b|| (float64, even rows taken as
  * for wd_wilson_solve).  Synchronous. */
 wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* params, const void* b, void* x,
                             wd_solver_info* info);
@@ -361,8 +369,8 @@ wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver_params* pa
  * float64) and stop when their residual estimate has fallen by params->delta
  * (> 0; else 1e-5); x_e and rhat are updated in float64 after each cycle until
  * ||rhat|| / ||b|| <= params->tol; then x_o = b_o + kappa D_oe x_e, and the full
- * residual ||b - M x|| / ||b||, recomputed in float64, is reported (it equals
- * ||rhat|| / ||b|| up to rounding).  A NaN or a cycle that reduces the residual
+ * residual ||b - M x|| / ||b|| is reported (it equals ||rhat|| / ||b|| up to
+ * rounding; taken as for wd_wilson_solve).  A NaN or a cycle that reduces the residual
  * less than tenfold hands x to wd_wilson_solve (fell_back = 1), whose float64
  * residual is reported.
  * With BF16 weights of widths 4 -> 8 -> ... -> 8 -> 4 the network keeps its hidden

@@ -249,7 +249,7 @@ wd_status op_M_red(wd_gauge g, double kappa, int subset, int dagger, int prec, c
     return reduce_partials(ctx, n, red_values(red), slot);
 }
 
-wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr, const void* doe_xe)
+wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr, const void* doe_xe, double schur_rr)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -264,6 +264,8 @@ wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr
         const void* in[2] = {b_e + hb, doe_xe};
         const double cr[2] = {1.0, kappa}, ci[2] = {0.0, 0.0};
         WD_TRY(blas_lincomb(ctx, G, 1, WD_F64, 2, in, cr, ci, x_e + hb, nullptr, false));
+        *rr = schur_rr;   // the even rows are bhat - Mhat x_e, whose norm^2 the solver holds
+        return WD_OK;
     } else {
         WD_TRY(hop_half(g, WD_F64, 1, 0, 1, x_e, hb, x_e + hb, hb, b_e + hb, hb, 1.0, kappa));
     }

@@ -14,9 +14,9 @@ namespace wd {
 typedef std::complex<double> cd;
 
 // doe_xe: set to a float64 half field holding D_oe x for the x returned, when one is at hand,
-// else to null.
+// else to null; *schur_rr then holds ||bhat - Mhat x||^2 of that same evaluation.
 static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& prm, const void* bhat, double bnorm2,
-                              void* x, wd_solver_info* info, const void** doe_xe)
+                              void* x, wd_solver_info* info, const void** doe_xe, double* schur_rr)
 {
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
@@ -150,7 +150,10 @@ static wd_status bicgstab_run(wd_gauge g, double kappa, const wd_solver_params& 
         doe_at_x = false;
         WD_TRY(true_res(&rr));
     }
-    if (doe_at_x) *doe_xe = doe;
+    if (doe_at_x) {
+        *doe_xe = doe;
+        *schur_rr = rr;
+    }
     info->true_resid = std::sqrt(rr / bnorm2);
     // the recomputed float64 residual decides: converged is WD_OK even after a breakdown
     // (the iterate it left may already meet tol), non-finite is WD_ENAN
@@ -182,6 +185,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
     WD_HIP(hipStreamSynchronize(ctx->stream));
+    HopTally tally(ctx, info);
     const auto t0 = std::chrono::steady_clock::now();
     *info = wd_solver_info{};
     const long long hb = (long long)half_bytes(G, WD_F64);
@@ -195,6 +199,7 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
     const double bb = ctx->hres[0];
     wd_status s = WD_OK;
     const void* doe_xe = nullptr;   // D_oe x_e from the last float64 residual, if at hand
+    double schur_rr = 0.0;          // and that residual's norm^2
     if (!std::isfinite(bb)) {   // NaN or Inf in the source: nothing to iterate on
         set_error("wd_bicgstab_solve: the source holds NaN or Inf");
         info->true_resid = info->true_resid_M = bb;
@@ -204,15 +209,15 @@ extern "C" wd_status wd_bicgstab_solve(wd_gauge g, double kappa, const wd_solver
         return WD_ENAN;
     }
     if (bb > 0.0) {
-        s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info, &doe_xe);
+        s = bicgstab_run(g, kappa, *params, bhat, bb, x_e, info, &doe_xe, &schur_rr);
         if (s != WD_OK && s != WD_ENOCONV) return s;
     } else {
         WD_TRY(blas_zero(ctx, G, 2, WD_F64, x));
     }
     double rr_full;
-    WD_TRY(eo_finish(g, kappa, b, x, &rr_full, doe_xe));   // x_o, then ||b - M x||^2 in float64
+    WD_TRY(eo_finish(g, kappa, b, x, &rr_full, doe_xe, schur_rr));   // x_o, then ||b - M x||^2 in float64
     info->true_resid_M = bb > 0 ? std::sqrt(rr_full / bb) : 0.0;
-    info->operator_applies++;
+    if (!doe_xe) info->operator_applies++;   // the closing float64 check applied the operator
     info->status = s;
     hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -112,7 +112,9 @@ std::string dslash_key(const Geom& g, const DslashCall& c)
 
 wd_status launch_dslash(wd_context ctx, const Geom& g, const DslashCall& c)
 {
-    return launch_dslash_tuned(ctx, g, c, tune_lookup(ctx, dslash_key(g, c)));
+    WD_TRY(launch_dslash_tuned(ctx, g, c, tune_lookup(ctx, dslash_key(g, c))));
+    ctx->hops += c.nrhs;
+    return WD_OK;
 }
 
 } // namespace wd

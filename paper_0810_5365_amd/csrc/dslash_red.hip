@@ -122,6 +122,7 @@ wd_status launch_dslash_red(wd_context ctx, const Geom& g, const DslashCall& c, 
     if (st == WD_EUNSUPPORTED)
         set_error("dslash: fused reduction %d is not built for precision %d %s the dagger", red, c.prec,
                   dag ? "with" : "without");
+    if (st == WD_OK) ctx->hops += 1;
     return st;
 }
 

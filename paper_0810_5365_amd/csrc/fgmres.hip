@@ -138,8 +138,9 @@ static wd_status fgmres_run(wd_gauge g, double kappa, const wd_solver_params& pr
         return WD_OK;
     };
     auto finish_x = [&](double* rr) -> wd_status {   // x_o, then the full residual in float64
-        WD_TRY(eo_finish(g, kappa, b, x, rr, doe_at_x ? doe : nullptr));
-        info->operator_applies++;
+        // (*rr on entry: the last Schur residual's norm^2, of this x_e when doe_at_x)
+        WD_TRY(eo_finish(g, kappa, b, x, rr, doe_at_x ? doe : nullptr, *rr));
+        if (!doe_at_x) info->operator_applies++;   // the closing float64 check applied the operator
         return WD_OK;
     };
     double rr;
@@ -352,6 +353,7 @@ wd_status wd_fgmres_solve(wd_gauge g, double kappa, const wd_solver_params* para
     Net net;
     if (nlayers > 0) WD_TRY(make_net("wd_fgmres_solve", nlayers, widths, weights, wprec, &net));
     WD_HIP(hipStreamSynchronize(g->ctx->stream));
+    HopTally tally(g->ctx, info);
     const auto t0 = std::chrono::steady_clock::now();
     bool fallback = false;
     wd_status s = fgmres_run(g, kappa, *params, restart, nlayers > 0 ? &net : nullptr, b, x, info, &fallback);

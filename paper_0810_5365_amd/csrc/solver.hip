@@ -137,9 +137,10 @@ static wd_status residual_wilson(const CGProblem& P, int pacc, const void* x, bo
 // already holds alpha p: x += xs in float64, the residual is recomputed from x and p' is formed
 // again from the old p (still in its buffer) with beta = rr / rr_s.
 // doe_xe (Wilson system, may be null): set to a float64 half field holding D_oe x for the x
-// returned, when one is at hand, else to null.
+// returned, when one is at hand, else to null; *schur_rr then holds ||bhat - Mhat x||^2 of that
+// same evaluation.
 static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x, wd_solver_info* info,
-                        const void** doe_xe = nullptr)
+                        const void** doe_xe = nullptr, double* schur_rr = nullptr)
 {
     wd_context ctx = P.g->ctx;
     const Geom& G = P.g->geom;
@@ -299,7 +300,10 @@ static wd_status cg_run(const CGProblem& P, const wd_solver_params& prm, void* x
     // ||bhat - Mhat x|| / ||b||; the general system ||c - A x|| / ||c||
     info->true_resid = wilson ? std::sqrt(ww / P.wnorm2) : std::sqrt(rr / cc);
     info->true_resid_M = wilson ? std::sqrt(ww / P.wnorm2) : -1.0;
-    if (doe_xe && wilson && doe_at_x) *doe_xe = doe;
+    if (doe_xe && schur_rr && wilson && doe_at_x) {
+        *doe_xe = doe;
+        *schur_rr = ww;
+    }
     if (status != WD_ENAN) cg_ritz_extremes(alphas, betas, &info->lambda_min, &info->lambda_max);
     if (status != WD_ENAN) status = converged() ? WD_OK : WD_ENOCONV;
     if (status == WD_ENOCONV)
@@ -346,6 +350,7 @@ wd_status wd_cg_solve(wd_gauge g, double kappa, wd_subset subset, const wd_solve
         return WD_EINVAL;
     }
     WD_HIP(hipStreamSynchronize(g->ctx->stream));
+    HopTally tally(g->ctx, info);
     const auto t0 = std::chrono::steady_clock::now();
     CGProblem P{g, kappa, (int)subset, b, nullptr, 0.0};
     wd_status s = cg_run(P, *params, x, info);
@@ -369,6 +374,7 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     wd_context ctx = g->ctx;
     const Geom& G = g->geom;
     WD_HIP(hipStreamSynchronize(ctx->stream));
+    HopTally tally(ctx, info);
     const auto t0 = std::chrono::steady_clock::now();
     const long long hb = (long long)half_bytes(G, WD_F64);
     const char* b_e = (const char*)b;
@@ -382,13 +388,14 @@ wd_status wd_wilson_solve(wd_gauge g, double kappa, const wd_solver_params* para
     const double bb = ctx->hres[0];
     CGProblem P{g, kappa, WD_EVEN, nullptr, bhat, bb};
     const void* doe_xe = nullptr;   // D_oe x_e from the last float64 residual, if at hand
-    wd_status s = cg_run(P, *params, x_e, info, &doe_xe);
+    double schur_rr = 0.0;          // and that residual's norm^2
+    wd_status s = cg_run(P, *params, x_e, info, &doe_xe, &schur_rr);
     if (s != WD_OK && s != WD_ENOCONV) return s;
     // x_o, then the full-system residual in float64
     double rr;
-    WD_TRY(eo_finish(g, kappa, b, x, &rr, doe_xe));
+    WD_TRY(eo_finish(g, kappa, b, x, &rr, doe_xe, schur_rr));
     info->true_resid_M = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-    info->operator_applies++;
+    if (!doe_xe) info->operator_applies++;   // the closing float64 check applied the operator
     hipStreamSynchronize(g->ctx->stream);   // synchronous: nothing of the solve left queued
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return s;

@@ -83,6 +83,9 @@ struct wd_context_s {
     double* hres_dev = nullptr;   // device address of hres, or null if it is not mapped
     std::map<std::string, wd::TuneParam> tune;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    // hopping-term applications queued on one parity (per rhs), plain and fused: the solvers
+    // report their difference as the operator work of a solve
+    long long hops = 0;
 };
 
 struct wd_gauge_s {

@@ -32,9 +32,23 @@ wd_status op_M_red_partials(wd_gauge g, double kappa, int subset, int dagger, in
 // D_oe x_e, then rr = ||b_e - (x_e - kappa D_eo x_o)||^2, the even rows of ||b - M x||^2.  The
 // odd rows are b_o - x_o + kappa D_oe x_e, zero by the construction of x_o up to its rounding,
 // and are not evaluated; the even rows test the x_o that was built.  doe_xe, if given, is
-// D_oe x_e already at hand (float64, odd half): x_o is then one linear combination instead of
-// a hop.  Fetched.
-wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr, const void* doe_xe = nullptr);
+// D_oe x_e of the float64 Schur residual the solver last computed at this x_e, whose norm^2 it
+// passes as schur_rr: x_o is then one linear combination instead of a hop, and the even rows,
+// b_e - x_e + kappa D_eo (b_o + kappa D_oe x_e) = bhat - Mhat x_e, are that residual, so *rr =
+// schur_rr without another launch.  Fetched.
+wd_status eo_finish(wd_gauge g, double kappa, const void* b, void* x, double* rr, const void* doe_xe = nullptr,
+                    double schur_rr = 0.0);
+// Sets info->hops, when the enclosing solver call returns, to the hopping-term applications
+// queued since its construction.
+struct HopTally {
+    wd_context ctx;
+    wd_solver_info* info;
+    long long h0;
+    HopTally(wd_context c, wd_solver_info* i) : ctx(c), info(i), h0(c->hops) {}
+    ~HopTally() { info->hops = ctx->hops - h0; }
+    HopTally(const HopTally&) = delete;
+    HopTally& operator=(const HopTally&) = delete;
+};
 // M^dagger M (FULL) or Mhat^dagger Mhat (EVEN / ODD)
 wd_status op_MdagM(wd_gauge g, double kappa, int subset, int prec, int nrhs, const void* in, void* out);
 

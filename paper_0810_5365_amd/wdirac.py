@@ -41,7 +41,7 @@ class WdSolverInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("reliable_updates", ctypes.c_int), ("operator_applies", ctypes.c_int),
                 ("status", ctypes.c_int), ("true_resid", ctypes.c_double), ("true_resid_M", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("cycles", ctypes.c_int), ("fell_back", ctypes.c_int),
-                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double)]
+                ("lambda_min", ctypes.c_double), ("lambda_max", ctypes.c_double), ("hops", ctypes.c_longlong)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -114,3 +114,32 @@ def test_fast_division_identity():
                                      dtype=np.uint64)])
         q = (n.astype(object) * m) >> (31 + l)
         assert all(int(a) == int(b) // d for a, b in zip(q, n))
+
+
+def test_ctypes_structs_match_the_header(w, tmp_path):
+    """The binding's ctypes mirrors of the header's structs have the C sizes and field offsets
+    (a C probe compiled against include/wdirac.h prints them)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [(w.WdLattice, "wd_lattice"), (w.WdSolverParams, "wd_solver_params"),
+               (w.WdSolverInfo, "wd_solver_info"), (w.WdBatchItem, "wd_batch_item")]
+    cname = lambda f: "in" if f == "in_" else f
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wdirac.h"', "int main(void) {"]
+    for cls, ct in structs:
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (ct, ct))
+        for f, _ in cls._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (ct, f, ct, cname(f)))
+    lines += ["return 0;", "}"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I" + os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                               text=True).stdout.splitlines())
+    for cls, ct in structs:
+        assert int(got[ct + " sizeof"]) == ctypes.sizeof(cls), ct
+        for f, _ in cls._fields_:
+            assert int(got["%s %s" % (ct, f)]) == getattr(cls, f).offset, (ct, f)

@@ -73,3 +73,14 @@ def test_closing_step_routes(env, solver, route):
         assert info.status == w.WD_OK and full <= 1.05 * TOL
     else:
         assert full > TOL
+    # hopping-term applications: bhat (1); the Wilson CG's c = Mhat^dag bhat (2, always formed);
+    # with no iteration, the residual of a non-zero guess (Wilson CG: Mhat x_e in float64 and
+    # Mhat^dag of it, 4; the other two: Mhat x_e, 2), and the closing hop pair (2) unless x_o
+    # reused D_oe x_e
+    no_iter = {("wilson", "zero_no_iter"): 1 + 2 + 2, ("wilson", "warm_no_iter"): 1 + 2 + 4,
+               ("bicgstab", "zero_no_iter"): 1 + 2, ("bicgstab", "warm_no_iter"): 1 + 2,
+               ("fgmres", "zero_no_iter"): 1 + 2, ("fgmres", "warm_no_iter"): 1 + 2}
+    if (solver, route) in no_iter:
+        assert info.hops == no_iter[(solver, route)], info.as_dict()
+    else:   # CG: four per iteration; BiCGstab and FGMRES: two per Mhat
+        assert info.hops >= (4 if solver == "wilson" else 2) * info.iters + 1, info.as_dict()
