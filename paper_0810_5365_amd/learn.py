@@ -178,7 +178,7 @@ def solve_compare(net, field, kappa, tol=1e-10, restart=16, seed=4242, maxiter=4
         res[name] = d
         return fx
 
-    prm = w.solver_params(tol=tol, maxiter=maxiter, sloppy=w.F32, delta=-1.0)   # library default (1e-4)
+    prm = w.solver_params(tol=tol, maxiter=maxiter, sloppy=w.F32, delta=-1.0)   # library default (1e-5)
     run("plain_cg_f32", lambda fx, info: w.wd_wilson_solve(field.g.handle, kappa, ctypes.byref(prm), fb.data_ptr(),
                                                             fx.data_ptr(), ctypes.byref(info)))
     prm_g = w.solver_params(tol=tol, maxiter=maxiter, sloppy=w.F32, delta=-1.0)   # library default (1e-5)

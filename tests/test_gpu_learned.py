@@ -67,6 +67,17 @@ def test_fgmres_unpreconditioned(env, delta):
     assert abs(res - info.true_resid_M) < 1e-12
 
 
+def test_fgmres_long_cycle(env):
+    """One cycle past 16 Krylov vectors (restart 40, cycle reduction 1e-9): the Gram-Schmidt
+    passes beyond the fused two-pass kernel's range, in several vector groups per sweep."""
+    w, ctx, dims, U, g = env
+    _LINKS[dims] = U
+    info, res = _solve(w, ctx, g, dims, 0.1248, restart=40, delta=1e-9)
+    assert info.status == w.WD_OK and info.fell_back == 0
+    assert res <= 1.05e-10, (res, info.as_dict())
+    assert info.iters > 16 and info.cycles <= 3, info.as_dict()
+
+
 @pytest.mark.parametrize("wprec,delta", [("f32", 1e-4), ("bf16", 1e-4), ("bf16", -1.0)])
 def test_fgmres_with_network(env, wprec, delta):
     import torch
