@@ -55,7 +55,7 @@
 extern "C" {
 #endif
 
-#define WD_ABI_VERSION 4
+#define WD_ABI_VERSION 5
 
 typedef enum {
     WD_OK = 0,

@@ -116,7 +116,7 @@ _PROTOS = {
 }
 
 _lib = None
-ABI_VERSION = 4   # the structures above match include/wdirac.h at this version
+ABI_VERSION = 5   # the structures above match include/wdirac.h at this version
 
 
 def _raw():

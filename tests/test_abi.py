@@ -39,7 +39,7 @@ def test_library_exports_every_declared_symbol(w):
 
 
 def test_abi_version_and_status_strings(w):
-    assert w.wd_abi_version() == w.ABI_VERSION == 4
+    assert w.wd_abi_version() == w.ABI_VERSION == 5
     for s in range(8):
         assert w.wd_status_string(s).startswith(b"WD_")
     assert b"unknown" in w.wd_status_string(99)
