@@ -255,6 +255,9 @@ def test_cg_even_odd_normal_equations(w, ctx, sloppy):
     assert info.status == w.WD_OK
     assert res <= 1.05 * tol, (res, info.as_dict())
     assert abs(res - info.true_resid) <= 1e-3 * tol + 1e-2 * res
+    # every counted application (an iteration's Mhat^dag Mhat, a residual's Mhat then Mhat^dag)
+    # is four hops on one parity
+    assert info.hops == 4 * info.operator_applies, info.as_dict()
 
 
 @pytest.mark.parametrize("sloppy", ["f64", "f32", "bf16"])
@@ -275,6 +278,8 @@ def test_cg_full_lattice_normal_equations(w, ctx, sloppy):
     assert info.status == w.WD_OK
     assert res <= 1.05 * tol, (res, info.as_dict())
     assert abs(res - info.true_resid) <= 1e-3 * tol + 1e-2 * res
+    # M^dag M on the full lattice is two full hops, each one hop per parity
+    assert info.hops == 4 * info.operator_applies, info.as_dict()
 
 
 @pytest.mark.parametrize("sloppy", ["f32", "bf16"])
